@@ -1,0 +1,513 @@
+/*
+ * ifdlbm_oracle.c -- TEST INFRASTRUCTURE ONLY (see ifdlbm_oracle.h).
+ *
+ * Plain serial FP64 IFDLBM for the lid-driven isosceles-trapezoid cavity,
+ * written from the paper, arXiv:2306.07603.  Every routine follows one
+ * equation or one Step of the calculational process in Section 4, in the
+ * paper's order and notation; there is no blocking, fusion or reordering.
+ * Build with -O2 -ffp-contract=off.
+ *
+ * Readings taken where the paper is silent, ambiguous or garbled (each one is
+ * pinned by a test where a pin exists):
+ *  R1  Eq. (2.8): the second-order term is divided by 2 c_s^4 (printed as
+ *      2 c_s^2); only this satisfies the moment design (A1) and inverts
+ *      Eq. (2.11).
+ *  R2  Eqs. (2.3)-(2.4): the collision operator is -(f - f_eq)/lambda, the
+ *      BGK term of Eq. (2.0); the conversions (2.15)-(2.18) follow from it.
+ *  R3  Eq. (2.7), c < 0 branch: the third point is Pi(chi + 2 dchi), the
+ *      mirror of the c >= 0 branch.
+ *  R4  The sign test of Eq. (2.7) uses the contravariant velocity component
+ *      of the direction being differenced, at that node (Section 4 notes it
+ *      varies with position); c = 0 takes the c >= 0 branch.
+ *  R5  c_s^2 = c^2 / 3 with c = 1 (the D2Q9 weights of Eq. (2.9) give
+ *      sum omega_k c_k c_k = I/3).
+ *  R6  Upwind points that would leave the grid (i = 1 or i = nx-2 in the
+ *      outward direction) fall back to the first-order one-sided difference.
+ *  R7  Boundary nodes use the non-equilibrium extrapolation named in
+ *      Section 4: X_b = f_eq(P_nb, u_wall) + (X_nb - f_eq(P_nb, u_nb)),
+ *      nb = the node one index inward (diagonal at corners).  It is applied
+ *      to the stage variable of each half of the step: f-bar at t + dt/2
+ *      (Step 4) and f-hat at t + dt (Step 6).
+ *  R8  The lid condition of Eq. (1.5) holds on the closed top edge, so the
+ *      two top corners move with the lid; bottom corners are at rest.
+ *  R9  Eq. (1.4) at zero shear: mu = K max(gamma^2, gamma_min^2)^((n-1)/2),
+ *      gamma^2 = 2 D:D.  Initial lambda_0 = U L / (Re c_s^2).
+ *  R10 Eq. (2.15.1): K = U^(2-n) L^n / Re with L = 1 (cavity height) and
+ *      U = |u_lid|.
+ *  R11 dt = cfl * min(dxi, deta) / c, dxi = 1/(nx-1), deta = 1/(ny-1).
+ *      Periodic directions hold N distinct nodes and use spacing 1/N.
+ *  R12 Step (2) uses the lambda stored with f-hat (the previous step's, as
+ *      Section 3 prescribes) both to recover f by Eq. (2.18) and in
+ *      Eq. (2.12); the new lambda is used by Steps (3)-(5).
+ *  R13 The half-step macroscopic quantities come from f-bar (Eqs. 2.10-2.11
+ *      allow it); they give f_eq(t + dt/2) for Eq. (2.17).
+ *  R14 Eq. (2.19) is evaluated over all nodes with the velocities and
+ *      pressures computed from f-hat before and after the step; 0/0 counts 0.
+ *  R15 Eq. (5.1): area integral with trapezoid weights in (xi, eta) times J.
+ */
+#include "ifdlbm_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------- lattice */
+
+/* Eq. (2.9): D2Q9 velocities (c = 1) and weights. */
+static const double CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const double CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+static const double OMEGA[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                                1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+static const double OMEGABAR[9] = {-5.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                                   1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+/* R5 */
+static const double CS2 = 1.0 / 3.0;
+
+void orc_lattice(double cx[9], double cy[9], double w[9], double wbar[9], double* cs2)
+{
+    for (int k = 0; k < 9; ++k) {
+        cx[k] = CX[k];
+        cy[k] = CY[k];
+        w[k] = OMEGA[k];
+        wbar[k] = OMEGABAR[k];
+    }
+    *cs2 = CS2;
+}
+
+/* Eq. (2.8), reading R1. */
+void orc_equilibrium(double P, double ux, double uy, double rho0, double feq[9])
+{
+    double uu = ux * ux + uy * uy;
+    for (int k = 0; k < 9; ++k) {
+        double cu = CX[k] * ux + CY[k] * uy;
+        /* u u : (c_k c_k - c_s^2 I) = (c_k . u)^2 - c_s^2 |u|^2 */
+        double uu_cc = cu * cu - CS2 * uu;
+        feq[k] = OMEGABAR[k] * P / CS2 + OMEGA[k] * rho0
+               + OMEGA[k] * (cu / CS2 + uu_cc / (2.0 * CS2 * CS2));
+    }
+}
+
+/* Eqs. (2.10) and (2.11). */
+void orc_moments(const double f[9], double rho0, double* P, double* ux, double* uy)
+{
+    double sx = 0.0, sy = 0.0, s = 0.0;
+    for (int k = 0; k < 9; ++k) {
+        sx += CX[k] * f[k];
+        sy += CY[k] * f[k];
+    }
+    for (int k = 1; k < 9; ++k) s += f[k];
+    *ux = sx;
+    *uy = sy;
+    *P = CS2 / OMEGABAR[0] * (-s + (1.0 - OMEGA[0]) * rho0 + OMEGA[0] / (2.0 * CS2) * (sx * sx + sy * sy));
+}
+
+/* ---------------------------------------------------------- parameters */
+
+static double cot_deg(double theta_deg)
+{
+    if (theta_deg == 90.0) return 0.0;   /* the unit square, exactly */
+    return 1.0 / tan(theta_deg * (M_PI / 180.0));
+}
+
+int orc_derive(const orc_params* p, orc_derived* d)
+{
+    if (p->nx < 5 || p->ny < 5) return -1;
+    if (!(p->theta_deg > 0.0 && p->theta_deg <= 90.0)) return -1;
+    if (!(p->n > 0.0) || !(p->re > 0.0) || !(p->cfl > 0.0)) return -1;
+    if (!(fabs(p->u_lid) > 0.0)) return -1;   /* Re of Eq. (2.15.1) needs U > 0 */
+    if (!(p->mix >= 0.0 && p->mix <= 1.0) || !(p->gamma_min > 0.0)) return -1;
+    if (p->bc_mode != ORC_CAVITY && p->theta_deg != 90.0) return -1;
+    if (p->bc_mode < ORC_CAVITY || p->bc_mode > ORC_PERIODIC) return -1;
+    /* R11 */
+    d->dxi = (p->bc_mode == ORC_CAVITY) ? 1.0 / (p->nx - 1) : 1.0 / p->nx;
+    d->deta = (p->bc_mode == ORC_PERIODIC) ? 1.0 / p->ny : 1.0 / (p->ny - 1);
+    d->dt = p->cfl * (d->dxi < d->deta ? d->dxi : d->deta) / 1.0;
+    /* R10: Re = U^(2-n) L^n / K with L = 1 */
+    double U = fabs(p->u_lid);
+    d->K = pow(U, 2.0 - p->n) / p->re;
+    d->cot = cot_deg(p->theta_deg);
+    /* R9: lambda_0 = U L / (Re c_s^2) */
+    d->lam0 = U / (p->re * CS2);
+    return 0;
+}
+
+/* ---------------------------------------------------------- geometry */
+
+/* Eq. (3.8.1) */
+void orc_node_xy(const orc_params* p, int i, int j, double* x, double* y)
+{
+    orc_derived d;
+    orc_derive(p, &d);
+    double xi = i * d.dxi, eta = j * d.deta;
+    double C = d.cot;
+    *x = 2.0 * C * xi * eta + xi - C * eta + C;
+    *y = eta;
+}
+
+/* Eqs. (3.2), (3.3), (3.4) with the derivatives of Eq. (3.8.2). */
+static void contravariant(const orc_derived* d, int i, int j, double cxi[9], double ceta[9], double* J)
+{
+    double xi = i * d->dxi, eta = j * d->deta;
+    double C = d->cot;
+    double x_xi = 2.0 * C * eta + 1.0;
+    double x_eta = 2.0 * C * xi - C;
+    double y_xi = 0.0, y_eta = 1.0;
+    double jac = x_xi * y_eta - x_eta * y_xi;
+    double xi_x = y_eta / jac, xi_y = -x_eta / jac;
+    double eta_x = -y_xi / jac, eta_y = x_xi / jac;
+    for (int k = 0; k < 9; ++k) {
+        cxi[k] = CX[k] * xi_x + CY[k] * xi_y;
+        ceta[k] = CX[k] * eta_x + CY[k] * eta_y;
+    }
+    if (J) *J = jac;
+}
+
+void orc_contravariant(const orc_params* p, int i, int j, double cxi[9], double ceta[9], double* J)
+{
+    orc_derived d;
+    orc_derive(p, &d);
+    contravariant(&d, i, j, cxi, ceta, J);
+}
+
+/* ---------------------------------------------------------- transport */
+
+/* Value of a field plane at (i, j), wrapping periodic directions. */
+static double at(const orc_params* p, const double* plane, int i, int j)
+{
+    if (p->bc_mode != ORC_CAVITY) i = (i % p->nx + p->nx) % p->nx;
+    if (p->bc_mode == ORC_PERIODIC) j = (j % p->ny + p->ny) % p->ny;
+    return plane[j * p->nx + i];
+}
+
+/* Eq. (2.5) along one grid direction: eps * central (2.6) + (1 - eps) *
+ * second-order upwind (2.7), readings R3, R4 and R6.  (di, dj) is the unit
+ * index step of the direction, h its spacing, c the contravariant velocity
+ * that selects the upwind side, and npts the node count along it. */
+static double mixed_derivative(const orc_params* p, const double* plane, int i, int j,
+                               int di, int dj, double h, double c, int pos, int npts, int periodic)
+{
+    double m1 = at(p, plane, i - di, j - dj);
+    double c0 = at(p, plane, i, j);
+    double p1 = at(p, plane, i + di, j + dj);
+    double central = (p1 - m1) / (2.0 * h);
+    double upwind;
+    if (c >= 0.0) {
+        if (periodic || pos >= 2)
+            upwind = (3.0 * c0 - 4.0 * m1 + at(p, plane, i - 2 * di, j - 2 * dj)) / (2.0 * h);
+        else
+            upwind = (c0 - m1) / h;
+    } else {
+        if (periodic || pos <= npts - 3)
+            upwind = -(3.0 * c0 - 4.0 * p1 + at(p, plane, i + 2 * di, j + 2 * dj)) / (2.0 * h);
+        else
+            upwind = -(c0 - p1) / h;
+    }
+    return p->mix * central + (1.0 - p->mix) * upwind;
+}
+
+/* Eq. (3.4): c_k . grad Phi_k = c_k,xi dPhi/dxi + c_k,eta dPhi/deta. */
+static double stream_term(const orc_params* p, const orc_derived* dd, const double* Phi, int k, int i, int j)
+{
+    orc_derived d = *dd;
+    size_t nn = (size_t)p->nx * p->ny;
+    const double* plane = Phi + (size_t)k * nn;
+    double cxi[9], ceta[9];
+    contravariant(&d, i, j, cxi, ceta, NULL);
+    int per_xi = p->bc_mode != ORC_CAVITY;
+    int per_eta = p->bc_mode == ORC_PERIODIC;
+    double term = 0.0;
+    if (cxi[k] != 0.0)
+        term += cxi[k] * mixed_derivative(p, plane, i, j, 1, 0, d.dxi, cxi[k], i, p->nx, per_xi);
+    if (ceta[k] != 0.0)
+        term += ceta[k] * mixed_derivative(p, plane, i, j, 0, 1, d.deta, ceta[k], j, p->ny, per_eta);
+    return term;
+}
+
+double orc_stream_term(const orc_params* p, const double* Phi, int k, int i, int j)
+{
+    orc_derived d;
+    orc_derive(p, &d);
+    return stream_term(p, &d, Phi, k, i, j);
+}
+
+/* ---------------------------------------------------------- boundary */
+
+static int is_boundary(const orc_params* p, int i, int j)
+{
+    int wall_i = (p->bc_mode == ORC_CAVITY) && (i == 0 || i == p->nx - 1);
+    int wall_j = (p->bc_mode != ORC_PERIODIC) && (j == 0 || j == p->ny - 1);
+    return wall_i || wall_j;
+}
+
+/* R7: the inward neighbour of a boundary node. */
+static void inward(const orc_params* p, int i, int j, int* ni, int* nj)
+{
+    *ni = i;
+    *nj = j;
+    if (p->bc_mode == ORC_CAVITY) {
+        if (i == 0) *ni = 1;
+        if (i == p->nx - 1) *ni = p->nx - 2;
+    }
+    if (p->bc_mode != ORC_PERIODIC) {
+        if (j == 0) *nj = 1;
+        if (j == p->ny - 1) *nj = p->ny - 2;
+    }
+}
+
+/* Eq. (1.5) with reading R8: the top row (corners included) moves with the lid. */
+static void wall_velocity(const orc_params* p, int i, int j, double* ux, double* uy)
+{
+    (void)i;
+    *ux = (j == p->ny - 1) ? p->u_lid : 0.0;
+    *uy = 0.0;
+}
+
+/* R7: fill every boundary node of the nine-plane field X from its inward
+ * neighbour: X_b = f_eq(P_nb, u_wall) + (X_nb - f_eq(P_nb, u_nb)), where
+ * (P_nb, u_nb) are the moments of X at nb. */
+static void nonequilibrium_extrapolation(const orc_params* p, double* X)
+{
+    size_t nn = (size_t)p->nx * p->ny;
+    for (int j = 0; j < p->ny; ++j)
+        for (int i = 0; i < p->nx; ++i) {
+            if (!is_boundary(p, i, j)) continue;
+            int ni, nj;
+            inward(p, i, j, &ni, &nj);
+            size_t nb = (size_t)nj * p->nx + ni, b = (size_t)j * p->nx + i;
+            double fnb[9], feq_nb[9], feq_w[9], P, ux, uy, wx, wy;
+            for (int k = 0; k < 9; ++k) fnb[k] = X[k * nn + nb];
+            orc_moments(fnb, p->rho0, &P, &ux, &uy);
+            orc_equilibrium(P, ux, uy, p->rho0, feq_nb);
+            wall_velocity(p, i, j, &wx, &wy);
+            orc_equilibrium(P, wx, wy, p->rho0, feq_w);
+            for (int k = 0; k < 9; ++k) X[k * nn + b] = feq_w[k] + (fnb[k] - feq_nb[k]);
+        }
+}
+
+/* ---------------------------------------------------------- per node */
+
+/* Step (7), Eq. (2.18): f from f-hat. */
+void orc_f_from_fhat_node(const double fh[9], const double feq[9], double lam, double dt, double f[9])
+{
+    for (int k = 0; k < 9; ++k) f[k] = 2.0 * lam / (2.0 * lam + dt) * fh[k] + dt / (2.0 * lam + dt) * feq[k];
+}
+
+/* Step (4), Eq. (2.17): f from f-bar. */
+void orc_f_from_fbar(const double fb[9], const double feq[9], double lam, double dt, double f[9])
+{
+    for (int k = 0; k < 9; ++k) f[k] = 4.0 * lam / (4.0 * lam + dt) * fb[k] + dt / (4.0 * lam + dt) * feq[k];
+}
+
+/* Step (3), Eq. (2.15), and Step (4), Eq. (2.16). */
+void orc_collide(const double fh[9], const double feq[9], double lam, double dt, double fhat_plus[9], double fbar_plus[9])
+{
+    for (int k = 0; k < 9; ++k) {
+        fhat_plus[k] = (2.0 * lam - dt) / (2.0 * lam + dt) * fh[k] + 2.0 * dt / (2.0 * lam + dt) * feq[k];
+        fbar_plus[k] = (4.0 * lam - dt) / (4.0 * lam + 2.0 * dt) * fh[k] + 3.0 * dt / (4.0 * lam + 2.0 * dt) * feq[k];
+    }
+}
+
+/* Step (2): lambda from f^(1) = f - f_eq, Eqs. (2.12)-(2.14) with Eq. (1.4),
+ * readings R9 and R12.  f is recovered from f-hat with the stored lambda by
+ * Eq. (2.18). */
+double orc_relaxation_time(const double fh[9], const double feq[9], double lam_old, double dt,
+                           double K, double n, double gamma_min)
+{
+    double f[9];
+    orc_f_from_fhat_node(fh, feq, lam_old, dt, f);
+    double sxx = 0.0, sxy = 0.0, syy = 0.0;   /* sum_k c c f^ne, Eq. (2.13) */
+    for (int k = 0; k < 9; ++k) {
+        double fne = f[k] - feq[k];
+        sxx += CX[k] * CX[k] * fne;
+        sxy += CX[k] * CY[k] * fne;
+        syy += CY[k] * CY[k] * fne;
+    }
+    /* Eq. (2.12): grad u + grad u^T = -(1/(lambda c_s^2)) sum c c f^ne */
+    double gxx = -sxx / (lam_old * CS2), gxy = -sxy / (lam_old * CS2), gyy = -syy / (lam_old * CS2);
+    /* Eq. (1.3.1): D = (grad u + grad u^T)/2; Eq. (1.4): mu = K (2 D:D)^((n-1)/2) */
+    double Dxx = 0.5 * gxx, Dxy = 0.5 * gxy, Dyy = 0.5 * gyy;
+    double gamma2 = 2.0 * (Dxx * Dxx + 2.0 * Dxy * Dxy + Dyy * Dyy);
+    double floor2 = gamma_min * gamma_min;
+    double mu = K * pow(gamma2 > floor2 ? gamma2 : floor2, 0.5 * (n - 1.0));
+    /* Eq. (2.14) */
+    return mu / CS2;
+}
+
+/* ---------------------------------------------------------- Step (1) */
+
+int orc_init(const orc_params* p, double* F, double* Lam)
+{
+    orc_derived d;
+    if (orc_derive(p, &d)) return -1;
+    size_t nn = (size_t)p->nx * p->ny;
+    for (int j = 0; j < p->ny; ++j)
+        for (int i = 0; i < p->nx; ++i) {
+            double ux = 0.0, uy = 0.0, feq[9];
+            if (p->bc_mode != ORC_PERIODIC) wall_velocity(p, i, j, &ux, &uy);
+            orc_equilibrium(0.0, ux, uy, p->rho0, feq);
+            size_t id = (size_t)j * p->nx + i;
+            for (int k = 0; k < 9; ++k) F[k * nn + id] = feq[k];
+            Lam[id] = d.lam0;
+        }
+    return 0;
+}
+
+/* ---------------------------------------------------------- Steps (2)-(8) */
+
+typedef struct {
+    double *fhat_plus, *fbar_plus, *fbar, *fhalf, *lam, *u_old, *v_old, *P_old;
+} workspace;
+
+static void velocities(const orc_params* p, const double* F, double* u, double* v, double* P)
+{
+    size_t nn = (size_t)p->nx * p->ny;
+    for (size_t id = 0; id < nn; ++id) {
+        double f[9];
+        for (int k = 0; k < 9; ++k) f[k] = F[k * nn + id];
+        orc_moments(f, p->rho0, &P[id], &u[id], &v[id]);
+    }
+}
+
+static int one_step(const orc_params* p, const orc_derived* d, double* F, double* Lam,
+                    workspace* w, double* res_u, double* res_p)
+{
+    const size_t nn = (size_t)p->nx * p->ny;
+    const double dt = d->dt;
+
+    velocities(p, F, w->u_old, w->v_old, w->P_old);
+
+    /* Steps (2)-(3) and the first half of Step (4), at every node. */
+    for (size_t id = 0; id < nn; ++id) {
+        double fh[9], feq[9], fhp[9], fbp[9], P, ux, uy;
+        for (int k = 0; k < 9; ++k) fh[k] = F[k * nn + id];
+        orc_moments(fh, p->rho0, &P, &ux, &uy);
+        orc_equilibrium(P, ux, uy, p->rho0, feq);
+        double lam = orc_relaxation_time(fh, feq, Lam[id], dt, d->K, p->n, p->gamma_min);
+        w->lam[id] = lam;
+        orc_collide(fh, feq, lam, dt, fhp, fbp);
+        for (int k = 0; k < 9; ++k) {
+            w->fhat_plus[k * nn + id] = fhp[k];
+            w->fbar_plus[k * nn + id] = fbp[k];
+        }
+    }
+
+    /* Step (4): half-step evolution, Eq. (3.7), at interior nodes. */
+    for (int j = 0; j < p->ny; ++j)
+        for (int i = 0; i < p->nx; ++i) {
+            if (is_boundary(p, i, j)) continue;
+            size_t id = (size_t)j * p->nx + i;
+            for (int k = 0; k < 9; ++k)
+                w->fbar[k * nn + id] = w->fbar_plus[k * nn + id] - 0.5 * dt * stream_term(p, d, w->fbar_plus, k, i, j);
+        }
+    /* boundary populations of f-bar (R7) */
+    nonequilibrium_extrapolation(p, w->fbar);
+    /* f(t + dt/2) by Eq. (2.17), with f_eq(t + dt/2) from the moments of f-bar (R13) */
+    for (size_t id = 0; id < nn; ++id) {
+        double fb[9], feq[9], f[9], P, ux, uy;
+        for (int k = 0; k < 9; ++k) fb[k] = w->fbar[k * nn + id];
+        orc_moments(fb, p->rho0, &P, &ux, &uy);
+        orc_equilibrium(P, ux, uy, p->rho0, feq);
+        orc_f_from_fbar(fb, feq, w->lam[id], dt, f);
+        for (int k = 0; k < 9; ++k) w->fhalf[k * nn + id] = f[k];
+    }
+
+    /* Step (5): full-step evolution, Eq. (3.6), at interior nodes. */
+    for (int j = 0; j < p->ny; ++j)
+        for (int i = 0; i < p->nx; ++i) {
+            if (is_boundary(p, i, j)) continue;
+            size_t id = (size_t)j * p->nx + i;
+            for (int k = 0; k < 9; ++k)
+                F[k * nn + id] = w->fhat_plus[k * nn + id] - dt * stream_term(p, d, w->fhalf, k, i, j);
+        }
+    /* Step (6): macroscopic quantities and the boundary populations (R7). */
+    nonequilibrium_extrapolation(p, F);
+    for (size_t id = 0; id < nn; ++id) Lam[id] = w->lam[id];
+
+    /* Step (8): global relative errors, Eq. (2.19), R14. */
+    double du2 = 0.0, u2 = 0.0, dp2 = 0.0, p2 = 0.0;
+    int finite = 1;
+    for (size_t id = 0; id < nn; ++id) {
+        double f[9], P, ux, uy;
+        for (int k = 0; k < 9; ++k) f[k] = F[k * nn + id];
+        orc_moments(f, p->rho0, &P, &ux, &uy);
+        if (!isfinite(P) || !isfinite(ux) || !isfinite(uy)) finite = 0;
+        du2 += (ux - w->u_old[id]) * (ux - w->u_old[id]) + (uy - w->v_old[id]) * (uy - w->v_old[id]);
+        u2 += ux * ux + uy * uy;
+        dp2 += (P - w->P_old[id]) * (P - w->P_old[id]);
+        p2 += P * P;
+    }
+    if (res_u) *res_u = (du2 == 0.0) ? 0.0 : sqrt(du2) / sqrt(u2);
+    if (res_p) *res_p = (dp2 == 0.0) ? 0.0 : sqrt(dp2) / sqrt(p2);
+    return finite ? 0 : -2;
+}
+
+int orc_run(const orc_params* p, double* F, double* Lam, long nsteps, double* res_u, double* res_p)
+{
+    orc_derived d;
+    if (orc_derive(p, &d)) return -1;
+    size_t nn = (size_t)p->nx * p->ny;
+    workspace w;
+    w.fhat_plus = malloc(9 * nn * sizeof(double));
+    w.fbar_plus = malloc(9 * nn * sizeof(double));
+    w.fbar = calloc(9 * nn, sizeof(double));
+    w.fhalf = malloc(9 * nn * sizeof(double));
+    w.lam = malloc(nn * sizeof(double));
+    w.u_old = malloc(nn * sizeof(double));
+    w.v_old = malloc(nn * sizeof(double));
+    w.P_old = malloc(nn * sizeof(double));
+    int rc = 0;
+    if (res_u) *res_u = 0.0;
+    if (res_p) *res_p = 0.0;
+    for (long s = 0; s < nsteps && rc == 0; ++s) rc = one_step(p, &d, F, Lam, &w, res_u, res_p);
+    free(w.fhat_plus);
+    free(w.fbar_plus);
+    free(w.fbar);
+    free(w.fhalf);
+    free(w.lam);
+    free(w.u_old);
+    free(w.v_old);
+    free(w.P_old);
+    return rc;
+}
+
+/* ---------------------------------------------------------- outputs */
+
+void orc_fields(const orc_params* p, const double* F, double* u, double* v, double* P)
+{
+    velocities(p, F, u, v, P);
+}
+
+void orc_f_from_fhat(const orc_params* p, const double* F, const double* Lam, double* f)
+{
+    orc_derived d;
+    orc_derive(p, &d);
+    size_t nn = (size_t)p->nx * p->ny;
+    for (size_t id = 0; id < nn; ++id) {
+        double fh[9], feq[9], fo[9], P, ux, uy;
+        for (int k = 0; k < 9; ++k) fh[k] = F[k * nn + id];
+        orc_moments(fh, p->rho0, &P, &ux, &uy);
+        orc_equilibrium(P, ux, uy, p->rho0, feq);
+        orc_f_from_fhat_node(fh, feq, Lam[id], d.dt, fo);
+        for (int k = 0; k < 9; ++k) f[k * nn + id] = fo[k];
+    }
+}
+
+double orc_kinetic_energy(const orc_params* p, const double* F)
+{
+    orc_derived d;
+    orc_derive(p, &d);
+    size_t nn = (size_t)p->nx * p->ny;
+    double e = 0.0;
+    for (int j = 0; j < p->ny; ++j)
+        for (int i = 0; i < p->nx; ++i) {
+            size_t id = (size_t)j * p->nx + i;
+            double f[9], P, ux, uy, cxi[9], ceta[9], J;
+            for (int k = 0; k < 9; ++k) f[k] = F[k * nn + id];
+            orc_moments(f, p->rho0, &P, &ux, &uy);
+            contravariant(&d, i, j, cxi, ceta, &J);
+            double wi = (p->bc_mode == ORC_CAVITY && (i == 0 || i == p->nx - 1)) ? 0.5 : 1.0;
+            double wj = (p->bc_mode != ORC_PERIODIC && (j == 0 || j == p->ny - 1)) ? 0.5 : 1.0;
+            e += 0.5 * wi * wj * J * d.dxi * d.deta * (ux * ux + uy * uy);
+        }
+    return e;
+}

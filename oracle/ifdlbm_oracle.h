@@ -1,0 +1,114 @@
+/*
+ * ifdlbm_oracle.h -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, serial, FP64 CPU implementation of the incompressible
+ * finite-difference lattice Boltzmann method (IFDLBM) of Chen, Chai, Zhao and
+ * Shi, "Numerical Simulation of Power-Law Fluid Flow in a Trapezoidal Cavity
+ * using the Incompressible Finite-Difference Lattice Boltzmann Method"
+ * (arXiv:2306.07603), for the lid-driven isosceles-trapezoid cavity.
+ *
+ * Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load this library.  It shares no source with the GPU library.
+ *
+ * Equation numbers are the paper's equation labels: (1.1)-(1.5) Section 2,
+ * (2.0)-(2.15.1) Section 3, (3.1)-(3.8.2) and the conversions (2.15)-(2.19)
+ * of the calculational process (Steps (1)-(8)) in Section 4, (A1)-(A12) the
+ * Chapman-Enskog appendix.
+ *
+ * State of a grid of nx * ny nodes: the nine planes F[k * nx*ny + j*nx + i]
+ * of the distribution f-hat (Eq. 2.3) and the plane Lam[j*nx + i] of the
+ * relaxation time lambda that produced it (Eq. 2.14).  Node (i, j) sits at
+ * xi = i*dxi, eta = j*deta in the computational square.
+ */
+#ifndef IFDLBM_ORACLE_H
+#define IFDLBM_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* bc_mode values.  ORC_CAVITY is the paper's problem (Eq. 1.5).  The two
+ * periodic modes are test-only geometries (theta must be 90 degrees) used to
+ * pin the oracle against closed forms and exact conservation. */
+enum { ORC_CAVITY = 0, ORC_COUETTE = 1, ORC_PERIODIC = 2 };
+
+typedef struct {
+    int    nx, ny;      /* nodes along xi and eta, boundary nodes included   */
+    double re;          /* generalised Reynolds number, Eq. (2.15.1), L = 1  */
+    double n;           /* power-law index, Eq. (1.4)                        */
+    double theta_deg;   /* top angle of the isosceles trapezoid, (0, 90]     */
+    double u_lid;       /* lid speed u0, Eq. (1.5); may be negative in tests */
+    double cfl;         /* dt = cfl * min(dxi, deta) / c, c = 1              */
+    double mix;         /* weight of the central scheme in Eq. (2.5)         */
+    double rho0;        /* constant density rho_0 of Eq. (2.8)               */
+    double gamma_min;   /* floor of the shear rate in Eq. (1.4)              */
+    int    bc_mode;     /* ORC_CAVITY, ORC_COUETTE or ORC_PERIODIC           */
+} orc_params;
+
+/* Derived constants of one run. */
+typedef struct {
+    double dxi, deta;   /* grid spacings of the computational square          */
+    double dt;          /* time step                                          */
+    double K;           /* consistency coefficient from Eq. (2.15.1)          */
+    double cot;         /* 1/tan(theta), exactly 0 at 90 degrees              */
+    double lam0;        /* initial relaxation time U L / (Re c_s^2)           */
+} orc_derived;
+
+/* Returns 0, or -1 when the parameters are outside the method's domain. */
+int  orc_derive(const orc_params* p, orc_derived* d);
+
+/* D2Q9 constants of Eq. (2.9): c_k (as doubles), omega_k, omegabar_k. */
+void orc_lattice(double cx[9], double cy[9], double w[9], double wbar[9], double* cs2);
+
+/* Eq. (2.8): incompressible equilibrium at (P, u). */
+void orc_equilibrium(double P, double ux, double uy, double rho0, double feq[9]);
+
+/* Eqs. (2.10)-(2.11): velocity and pressure from any of f, f-bar, f-hat. */
+void orc_moments(const double f[9], double rho0, double* P, double* ux, double* uy);
+
+/* Per-node conversions of the calculational process (Section 4):
+ * Eq. (2.18) f from f-hat, Eq. (2.17) f from f-bar, Eqs. (2.15)-(2.16) the
+ * post-collision f-hat+ and f-bar+, and Step (2), lambda from the
+ * non-equilibrium part by Eqs. (2.12)-(2.14) and (1.4) given the lambda that
+ * produced f-hat. */
+void   orc_f_from_fhat_node(const double fh[9], const double feq[9], double lam, double dt, double f[9]);
+void   orc_f_from_fbar(const double fb[9], const double feq[9], double lam, double dt, double f[9]);
+void   orc_collide(const double fh[9], const double feq[9], double lam, double dt,
+                   double fhat_plus[9], double fbar_plus[9]);
+double orc_relaxation_time(const double fh[9], const double feq[9], double lam_old, double dt,
+                           double K, double n, double gamma_min);
+
+/* Eq. (3.8.1): physical position of node (i, j). */
+void orc_node_xy(const orc_params* p, int i, int j, double* x, double* y);
+
+/* Eqs. (3.2)-(3.8.2): contravariant velocities (c_k,xi , c_k,eta) at (i, j),
+ * and the Jacobian J of Eq. (3.3). */
+void orc_contravariant(const orc_params* p, int i, int j, double cxi[9], double ceta[9], double* J);
+
+/* Mixed-difference transport term c_k,xi dPhi_k/dxi + c_k,eta dPhi_k/deta of
+ * Eqs. (2.5)-(2.7) and (3.4) at interior node (i, j), for population k of
+ * the nine-plane field Phi. */
+double orc_stream_term(const orc_params* p, const double* Phi, int k, int i, int j);
+
+/* Step (1): rest state plus moving lid; F = f-hat = f_eq, Lam = lambda_0. */
+int  orc_init(const orc_params* p, double* F, double* Lam);
+
+/* Steps (2)-(8), nsteps times, in place.  res_u / res_p (may be NULL) receive
+ * the global relative errors of Eq. (2.19) of the last step.  Returns 0, or
+ * -1 on bad parameters, or -2 if the state became non-finite. */
+int  orc_run(const orc_params* p, double* F, double* Lam, long nsteps, double* res_u, double* res_p);
+
+/* Macroscopic fields u, v, P (each nx*ny, [j][i]) of the state. */
+void orc_fields(const orc_params* p, const double* F, double* u, double* v, double* P);
+
+/* Step (7), Eq. (2.18): the distribution f from f-hat and the stored lambda. */
+void orc_f_from_fhat(const orc_params* p, const double* F, const double* Lam, double* f);
+
+/* Eq. (5.1): kinetic energy 1/2 sum |u|^2 dA over the physical cavity,
+ * trapezoid-rule weights in (xi, eta) times the Jacobian J. */
+double orc_kinetic_energy(const orc_params* p, const double* F);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
