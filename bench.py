@@ -1,0 +1,153 @@
+"""Throughput of the IFDLBM time step on one MI355X.
+
+Workload (one "step" = one time step of every cavity): the seeded batch of
+256 lid-driven isosceles-trapezoid cavities of uneven size and parameters
+(sides 65/129/257/513, Re 100-5000 log-uniform, n 0.5-1.5, theta 40-90 deg,
+lid 0.1, CFL 0.5), FP32 storage and arithmetic, FP64 residual sums of
+Eq. (2.19) every 100 steps, all cavities in one launch per step, replayed
+from a captured HIP graph.  Inputs start resident in HBM (Step 1 on the
+device).  Printed on one JSON line: MLUPS, the roofline record of the step
+kernel (algorithmic bytes per launch over its average duration, from HIP
+events on the stream the library launches on), the same batch in FP64 with
+one launch per cavity and no graph ("plain FP64", and the speedup over it),
+and the serial CPU oracle timed on a bounded sample of the batch.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS & % HBM roofline, FP32-batched vs plain FP64 on GPU at ≤1e-5 vs oracle"
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, published
+WORKLOAD = ("256-cavity uneven batch: sides {65,129,257,513}, Re log-uniform [100,5000], n uniform [0.5,1.5], "
+            "theta uniform [40,90] deg, lid 0.1, CFL 0.5; FP32 storage, FP64 residual sums every 100 steps, "
+            "one launch per step, HIP-graph replay")
+
+
+def log(msg: str) -> None:
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def time_steps(M, h, stream, steps: int, warmup: int):
+    import torch
+    M.ifdlbm_step(h, warmup)
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record(stream)
+    M.ifdlbm_step(h, steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, start.elapsed_time(end)
+
+
+def cpu_baseline(specs, steps: int):
+    """The serial FP64 oracle on one cavity of each side of the batch."""
+    import oracle as O
+    picks = []
+    for side in (65, 129, 257, 513):
+        for s in specs:
+            if s.n_xi == side:
+                picks.append(s)
+                break
+    nodes = 0
+    t0 = time.perf_counter()
+    for s in picks:
+        p = O.Params(nx=s.n_xi, ny=s.n_eta, re=s.re, n=s.n, theta_deg=s.theta_deg, u_lid=s.u_lid)
+        F, L = O.init(p)
+        O.run(p, F, L, steps)
+        nodes += s.n_xi * s.n_eta * steps
+    dt = time.perf_counter() - t0
+    return {"value": nodes / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": "serial FP64 oracle, %d steps of one cavity of each side (65, 129, 257, 513) of the batch, "
+                      "%.1f s" % (steps, dt)}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--kernel", default="fused", choices=["fused", "staged"])
+    ap.add_argument("--residual-every", type=int, default=100)
+    ap.add_argument("--graph-steps", type=int, default=100)
+    ap.add_argument("--plain-steps", type=int, default=100, help="steps of the plain FP64 comparison run (0: skip)")
+    ap.add_argument("--cpu-steps", type=int, default=20, help="steps of the CPU oracle sample (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (cavities are independent; "
+              "the batch would shard across GPUs with no communication).", file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_2306_07603_amd as M
+    from paper_2306_07603_amd import workloads as W
+
+    assert torch.cuda.is_available(), "no GPU visible"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    specs = W.batch_sweep()
+    cav = [M.Cavity(**s.__dict__) for s in specs]
+
+    opt = M.ifdlbm_default_options(precision="fp32", kernel=args.kernel, residual_every=args.residual_every,
+                                   graph_steps=args.graph_steps, batched=1, hip_stream=stream.cuda_stream)
+    h = M.ifdlbm_create(cav, opt)
+    info = M.ifdlbm_info(h)
+    log("created %d cavities, %d nodes per step, %d work items" % (info["n_cavities"], info["nodes"], info["work_items"]))
+    wall, ev_ms = time_steps(M, h, stream, args.steps, args.warmup)
+    ru, rp = M.ifdlbm_get_residuals(h)
+    import numpy as np
+    assert np.all(np.isfinite(ru)) and np.all(np.isfinite(rp)), "non-finite residuals"
+    nodes = info["nodes"]
+    mlups = nodes * args.steps / wall / 1e6
+    launches = args.steps * info["launches_per_step"]
+    kernel_ms = ev_ms / launches
+    alg_bytes = nodes * info["alg_bytes_per_node"]
+    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
+    log("fp32 batched: %.1f MLUPS, %.3f ms/step, kernel %.3f ms, %.0f GB/s" % (mlups, wall * 1e3 / args.steps, kernel_ms, achieved))
+    h.close()
+
+    plain = None
+    if args.plain_steps > 0:
+        opt64 = M.ifdlbm_default_options(precision="fp64", kernel=args.kernel, residual_every=args.residual_every,
+                                         graph_steps=0, batched=0, hip_stream=stream.cuda_stream)
+        h64 = M.ifdlbm_create(cav, opt64)
+        wall64, ev64 = time_steps(M, h64, stream, args.plain_steps, min(args.warmup, 20))
+        mlups64 = nodes * args.plain_steps / wall64 / 1e6
+        plain = {"value": mlups64, "unit": "MLUPS", "ms_per_step": wall64 * 1e3 / args.plain_steps,
+                 "steps": args.plain_steps, "config": "same batch, FP64, one launch per cavity per step, no graph"}
+        log("fp64 plain: %.1f MLUPS" % mlups64)
+        h64.close()
+
+    cpu = cpu_baseline(specs, args.cpu_steps) if args.cpu_steps > 0 else None
+    if cpu:
+        log("cpu oracle: %.3f MLUPS" % cpu["value"])
+
+    out = {
+        "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": WORKLOAD, "cavities": len(specs), "nodes_per_step": nodes, "kernel": args.kernel,
+                   "residual_every": args.residual_every, "graph_steps": args.graph_steps},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel_ms": kernel_ms, "alg_bytes_per_launch": alg_bytes,
+                     "alg_bytes_per_node": info["alg_bytes_per_node"]},
+        "fp64_plain": plain,
+        "speedup_vs_fp64_plain": (mlups / plain["value"]) if plain else None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

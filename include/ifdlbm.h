@@ -1,0 +1,166 @@
+/*
+ * ifdlbm.h -- C ABI of the MI355X (gfx950) IFDLBM library, libifdlbm.so.
+ *
+ * The library advances the incompressible finite-difference lattice
+ * Boltzmann method (IFDLBM) of Chen, Chai, Zhao and Shi (arXiv:2306.07603)
+ * for power-law fluid in lid-driven isosceles-trapezoid cavities, many
+ * cavities at once, on one GPU.  One time step is the calculational process
+ * of Section 4, Steps (2)-(6): relaxation time from the non-equilibrium
+ * moments (Eqs. 2.12-2.14, 1.4), collision (Eqs. 2.15-2.16), half-step
+ * mixed-difference streaming on the body-fitted grid (Eqs. 3.7, 2.5-2.7,
+ * 3.2-3.8.2) with f(t+dt/2) from Eq. (2.17), full-step streaming (Eq. 3.6),
+ * and non-equilibrium-extrapolation walls and lid (Eq. 1.5).  Step (8), the
+ * global relative error of Eq. (2.19), is evaluated every residual_every steps;
+ * its E(P) is taken on the pressure with the spatial mean removed (the level
+ * of P is a gauge of the incompressible model, and the extrapolation walls
+ * let it drift at a constant rate once u is steady).
+ *
+ * Conventions for every call:
+ *  - Return 0 (IFDLBM_OK) on success or a negative IFDLBM_E* code.  No C++
+ *    exception or abort crosses the ABI.  ifdlbm_strerror(code) names a code;
+ *    ifdlbm_last_error() gives the calling thread's last message.
+ *  - The library owns the handle and all device memory (freed by
+ *    ifdlbm_destroy).  The caller owns every host array passed in; the
+ *    library copies in or out and keeps no pointer to it.
+ *  - Host arrays of one cavity are row-major [j][i] with i (xi, along the
+ *    lid) fastest: n_eta rows of n_xi values.  Distribution arrays are
+ *    [k][j][i], k = 0..8 in the order of Eq. (2.9).
+ *  - Work is enqueued on the handle's HIP stream (options.hip_stream, or the
+ *    null stream).  Calls that return host data synchronise that stream.
+ *  - A handle must not be used by two threads at once.
+ */
+#ifndef IFDLBM_H
+#define IFDLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Opaque handle: a batch of cavities with their device state. */
+typedef struct ifdlbm_s ifdlbm_t;
+
+/* ---------------------------------------------------------------- codes */
+#define IFDLBM_OK             0
+#define IFDLBM_EINVAL        -1   /* an argument is outside its documented domain          */
+#define IFDLBM_ENOMEM        -2   /* device or host allocation failed                      */
+#define IFDLBM_EDEVICE       -3   /* a HIP call failed (text in ifdlbm_last_error)          */
+#define IFDLBM_EDIVERGED     -4   /* a cavity's state became non-finite; others continue    */
+#define IFDLBM_ENOTCONVERGED -5   /* max_steps reached before tol; outputs are valid        */
+
+/* storage / compute precision (options.precision) */
+#define IFDLBM_FP64     0   /* FP64 distributions and relaxation time, FP64 arithmetic           */
+#define IFDLBM_FP32     1   /* FP32 deviations f-hat - omega_k rho0, FP32 arithmetic             */
+#define IFDLBM_FP16DEV  2   /* FP16 scaled deviations (f-hat - omega_k rho0)/omega_k, FP32 lambda
+                               and FP32 arithmetic                                                 */
+
+/* kernel schedule (options.kernel) */
+#define IFDLBM_KERNEL_FUSED    0   /* one fused launch per step (default)                        */
+#define IFDLBM_KERNEL_STAGED   1   /* five staged launches per step through HBM temporaries       */
+
+/* cavity status (ifdlbm_status) */
+#define IFDLBM_STATUS_RUNNING       0
+#define IFDLBM_STATUS_CONVERGED     1
+#define IFDLBM_STATUS_DIVERGED      2
+#define IFDLBM_STATUS_NOT_CONVERGED 3
+
+/* One lid-driven isosceles-trapezoid cavity (Section 2; Eq. 3.8.1). */
+typedef struct {
+    int32_t n_xi;       /* nodes along the lid direction xi, walls included, >= 5                   */
+    int32_t n_eta;      /* nodes along the height eta, bottom and lid included, >= 5                */
+    double  re;         /* generalised Reynolds number U^(2-n) L^n / K of Eq. (2.15.1), L = 1, > 0  */
+    double  n;          /* power-law index of Eq. (1.4), > 0 (n = 1: Newtonian)                      */
+    double  theta_deg;  /* top angle theta of the trapezoid in degrees, (0, 90]; 90 = unit square    */
+    double  u_lid;      /* lid velocity u0 of Eq. (1.5), nonzero (negative: lid moves towards -x)   */
+} ifdlbm_cavity;
+
+typedef struct {
+    int32_t precision;      /* IFDLBM_FP64 | IFDLBM_FP32 | IFDLBM_FP16DEV                             */
+    double  cfl;            /* dt = cfl * min(dxi, deta) / c with c = 1, > 0 (paper: 0.5)             */
+    double  mix;            /* weight of the central scheme in Eq. (2.5), [0, 1] (default 0.5)       */
+    double  rho0;           /* constant density of Eq. (2.8) (default 1); u and P do not depend on it */
+    double  gamma_min;      /* floor of the shear rate in Eq. (1.4), > 0 (default 1e-6)              */
+    int32_t residual_every; /* evaluate Eq. (2.19) every this many steps, >= 1 (paper: 1)             */
+    int32_t kernel;         /* IFDLBM_KERNEL_FUSED | IFDLBM_KERNEL_STAGED                             */
+    int32_t batched;        /* 1: all cavities in one launch per step; 0: one launch per cavity       */
+    int32_t graph_steps;    /* > 0: replay steps from a captured HIP graph of this many steps         */
+    void*   hip_stream;     /* hipStream_t to enqueue on, or NULL for the null stream                 */
+} ifdlbm_options;
+
+/* Sizes of a handle's work, for throughput and roofline accounting. */
+typedef struct {
+    int32_t n_cavities;
+    int32_t n_active;           /* cavities still stepping (not converged, not diverged)               */
+    int64_t nodes;              /* sum over active cavities of n_xi * n_eta                            */
+    int64_t state_bytes;        /* device bytes of one copy of the state (f-hat and lambda)            */
+    double  alg_bytes_per_node; /* algorithmic HBM bytes per node update: state read + written once   */
+    int32_t launches_per_step;  /* kernel launches per time step (residual steps add the reduction)    */
+    int64_t work_items;         /* workgroups of the step kernel                                       */
+} ifdlbm_info_t;
+
+/* Fills *opt with the defaults: FP64, cfl 0.5, mix 0.5, rho0 1, gamma_min 1e-6, residual_every 1,
+   fused kernel, batched, no graph, null stream. */
+int ifdlbm_default_options(ifdlbm_options* opt);
+
+/* Validates cav[0..n_cav) and *opt, builds the metric terms of Eqs. (3.2)-(3.8.2) in FP64 on the host,
+   allocates the device state and applies Step (1): u = 0, P = 0 except u = (u_lid, 0) on the top row
+   (corners included), f-hat = f_eq, lambda = U / (Re c_s^2).  *out receives the handle.
+   Errors: EINVAL (bad argument, nothing allocated), ENOMEM, EDEVICE. */
+int ifdlbm_create(const ifdlbm_cavity* cav, int32_t n_cav, const ifdlbm_options* opt, ifdlbm_t** out);
+
+/* Enqueues n_steps >= 0 time steps of every running cavity (Section 4, Steps (2)-(6)); does not wait.
+   Residuals of Eq. (2.19) are updated on steps that are multiples of residual_every. */
+int ifdlbm_step(ifdlbm_t* h, int64_t n_steps);
+
+/* Waits for all enqueued work of the handle. */
+int ifdlbm_sync(ifdlbm_t* h);
+
+/* Steps until both global relative errors E(u), E(P) of Eq. (2.19) are <= tol for every cavity, or
+   max_steps more steps were taken.  Converged cavities stop stepping (status CONVERGED); a cavity whose
+   state becomes non-finite stops (status DIVERGED) while the others continue.  steps_done, res_u and
+   res_p are caller-owned arrays of n_cav entries (any may be NULL) receiving, per cavity, the steps taken
+   in this call and the last residuals.  Returns OK, ENOTCONVERGED (some cavity hit max_steps) or
+   EDIVERGED (some cavity diverged; takes precedence). */
+int ifdlbm_run_to_steady(ifdlbm_t* h, double tol, int64_t max_steps,
+                         int64_t* steps_done, double* res_u, double* res_p);
+
+/* Last evaluated residuals E(u), E(P) of Eq. (2.19) for every cavity (arrays of n_cav, caller-owned). */
+int ifdlbm_get_residuals(ifdlbm_t* h, double* res_u, double* res_p);
+
+/* Velocity (u, v) and pressure P of Eqs. (2.10)-(2.11) of cavity cav, FP64, into caller-owned host
+   arrays of n_eta * n_xi values each (any may be NULL). */
+int ifdlbm_get_fields(ifdlbm_t* h, int32_t cav, double* u, double* v, double* p);
+
+/* As ifdlbm_get_fields, into caller-owned device arrays (dtype 0: float64, 1: float32), enqueued on the
+   handle's stream without waiting. */
+int ifdlbm_get_fields_device(ifdlbm_t* h, int32_t cav, void* u, void* v, void* p, int32_t dtype);
+
+/* Kinetic energy of Eq. (5.1) of cavity cav: 1/2 sum |u|^2 over the physical area, trapezoid weights in
+   (xi, eta) times the Jacobian J = 1 + 2 eta cot(theta). */
+int ifdlbm_kinetic_energy(ifdlbm_t* h, int32_t cav, double* energy);
+
+/* Checkpoint / restore of cavity cav: f-hat as FP64 [k][j][i] (9 * n_eta * n_xi values, rho0 included)
+   and lambda [j][i] (n_eta * n_xi values), caller-owned host arrays.  set_state resets the cavity's
+   status to RUNNING.  With FP32 / FP16DEV storage the values are rounded to the storage format. */
+int ifdlbm_get_state(ifdlbm_t* h, int32_t cav, double* fhat, double* lambda);
+int ifdlbm_set_state(ifdlbm_t* h, int32_t cav, const double* fhat, const double* lambda);
+
+/* IFDLBM_STATUS_* of cavity cav, or a negative error code. */
+int ifdlbm_status(ifdlbm_t* h, int32_t cav);
+
+/* Work sizes of the handle (see ifdlbm_info_t). */
+int ifdlbm_info(ifdlbm_t* h, ifdlbm_info_t* info);
+
+/* Frees the handle and its device memory; NULL-safe. */
+void ifdlbm_destroy(ifdlbm_t* h);
+
+/* Static text for an IFDLBM_E* code, and the calling thread's last error message. */
+const char* ifdlbm_strerror(int code);
+const char* ifdlbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

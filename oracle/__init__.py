@@ -78,6 +78,7 @@ def load(path: str):
     L.orc_f_from_fhat.argtypes = [P, _D, _D, _D]
     L.orc_kinetic_energy.argtypes = [P, _D]
     L.orc_kinetic_energy.restype = ctypes.c_double
+    L.orc_residuals.argtypes = [P, _D, _D, _D, _D, _D]
     L.orc_f_from_fhat_node.argtypes = [_D, _D, ctypes.c_double, ctypes.c_double, _D]
     L.orc_f_from_fbar.argtypes = [_D, _D, ctypes.c_double, ctypes.c_double, _D]
     L.orc_collide.argtypes = [_D, _D, ctypes.c_double, ctypes.c_double, _D, _D]
@@ -219,6 +220,14 @@ def run(p: Params, F: np.ndarray, Lam: np.ndarray, nsteps: int):
     if rc == -2:
         raise FloatingPointError("oracle state became non-finite")
     return ru.value, rp.value
+
+
+def residuals(p: Params, F_old: np.ndarray, F_new: np.ndarray):
+    """Eq. (2.19) between two states: (E(u), E(P), E(P) with the mean of P removed)."""
+    eu, ep, eg = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    lib().orc_residuals(ctypes.byref(p.c()), _ptr(np.ascontiguousarray(F_old)), _ptr(np.ascontiguousarray(F_new)),
+                        ctypes.byref(eu), ctypes.byref(ep), ctypes.byref(eg))
+    return eu.value, ep.value, eg.value
 
 
 def fields(p: Params, F: np.ndarray):

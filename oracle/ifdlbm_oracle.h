@@ -98,6 +98,11 @@ int  orc_init(const orc_params* p, double* F, double* Lam);
  * -1 on bad parameters, or -2 if the state became non-finite. */
 int  orc_run(const orc_params* p, double* F, double* Lam, long nsteps, double* res_u, double* res_p);
 
+/* Eq. (2.19) between two states: E(u), E(P), and E(P) of the pressure with
+ * its spatial mean removed (reading R16). */
+void orc_residuals(const orc_params* p, const double* F_old, const double* F_new,
+                   double* e_u, double* e_p, double* e_p_gauge);
+
 /* Macroscopic fields u, v, P (each nx*ny, [j][i]) of the state. */
 void orc_fields(const orc_params* p, const double* F, double* u, double* v, double* P);
 

@@ -1,0 +1,713 @@
+// api.hip -- the C ABI of libifdlbm.so (declared in include/ifdlbm.h):
+// argument validation, FP64 metric precompute, device memory, work lists,
+// the time loop with its residual schedule, HIP graph replay, and the
+// steady-state driver with per-cavity retirement.
+#include "ifdlbm.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ifdlbm_internal.h"
+
+using namespace ifd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+#define IFD_HIP(expr)                                                                                   \
+    do {                                                                                                \
+        hipError_t e_ = (expr);                                                                         \
+        if (e_ != hipSuccess) return fail(IFDLBM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr double kCs2 = 1.0 / 3.0;
+
+// Rows per segment of the fused kernel's work items (the columns per strip
+// are at most kStripOut).
+constexpr int kSegRows = 64;
+
+int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+size_t f_elem_size(int prec) { return prec == P_FP64 ? 8 : (prec == P_FP32 ? 4 : 2); }
+size_t l_elem_size(int prec) { return prec == P_FP64 ? 8 : 4; }
+size_t t_elem_size(int prec) { return prec == P_FP64 ? 8 : 4; }
+
+// 1/tan(theta) with theta in degrees; exactly 0 for the square.
+double cot_deg(double theta_deg)
+{
+    if (theta_deg == 90.0) return 0.0;
+    return 1.0 / std::tan(theta_deg * (M_PI / 180.0));
+}
+
+}  // namespace
+
+struct ifdlbm_s {
+    int n_cav = 0;
+    ifdlbm_options opt{};
+    std::vector<ifdlbm_cavity> cav;
+    std::vector<CavityDesc> desc;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+
+    size_t f_elems = 0, l_elems = 0;
+    void* d_f[2] = {nullptr, nullptr};
+    void* d_l[2] = {nullptr, nullptr};
+    int cur = 0;
+    CavityDesc* d_desc = nullptr;
+    double* d_geo = nullptr;
+    float* d_geo32 = nullptr;
+    void *d_hp = nullptr, *d_bp = nullptr, *d_fb = nullptr, *d_ln = nullptr;   // staged temporaries
+
+    // node blocks of every cavity (initialisation) and of the running ones (staged step)
+    std::vector<NodeBlock> all_blocks;
+    NodeBlock* d_all_blocks = nullptr;
+    std::vector<NodeBlock> act_blocks;
+    NodeBlock* d_act_blocks = nullptr;
+    // strip items of the running cavities (fused step)
+    std::vector<StripItem> act_items;
+    StripItem* d_act_items = nullptr;
+    size_t max_units = 0;
+    std::vector<int32_t> unit_first, unit_count;   // per cavity, in the active unit list
+    int32_t *d_unit_first = nullptr, *d_unit_count = nullptr;
+    double* d_partial = nullptr;
+    double* d_res = nullptr;                        // n_cav * kPartials
+    double* d_scratch = nullptr;                    // 10 * max nodes doubles
+    size_t scratch_elems = 0;
+
+    std::vector<int> status;
+    std::vector<double> res_u, res_p;
+    int64_t step_count = 0;
+    hipGraphExec_t graph_exec = nullptr;
+    bool graph_dirty = true;
+};
+
+namespace {
+
+int units_per_step(const ifdlbm_s* h) { return h->opt.kernel == IFDLBM_KERNEL_STAGED ? 5 : 1; }
+
+// Rebuild the unit lists of the running cavities (after creation, retirement or restore).
+int rebuild_worklists(ifdlbm_s* h)
+{
+    h->act_blocks.clear();
+    h->act_items.clear();
+    for (int c = 0; c < h->n_cav; ++c) {
+        const bool run = h->desc[c].active != 0;
+        if (h->opt.kernel == IFDLBM_KERNEL_STAGED) {
+            h->unit_first[c] = (int32_t)h->act_blocks.size();
+            if (run) {
+                const int nn = h->desc[c].nx * h->desc[c].ny;
+                for (int n = 0; n < nn; n += kNodeBlock) h->act_blocks.push_back({c, n});
+            }
+            h->unit_count[c] = (int32_t)h->act_blocks.size() - h->unit_first[c];
+        } else {
+            h->unit_first[c] = (int32_t)h->act_items.size();
+            if (run) {
+                const CavityDesc& d = h->desc[c];
+                const int ns = ceil_div(d.nx, kStripOut), ng = ceil_div(d.ny, kSegRows);
+                for (int g = 0; g < ng; ++g)
+                    for (int s = 0; s < ns; ++s)
+                        h->act_items.push_back({c, (int16_t)(s * d.nx / ns), (int16_t)((s + 1) * d.nx / ns),
+                                                g * d.ny / ng, (g + 1) * d.ny / ng});
+            }
+            h->unit_count[c] = (int32_t)h->act_items.size() - h->unit_first[c];
+        }
+    }
+    if (!h->act_blocks.empty())
+        IFD_HIP(hipMemcpyAsync(h->d_act_blocks, h->act_blocks.data(), h->act_blocks.size() * sizeof(NodeBlock),
+                               hipMemcpyHostToDevice, h->stream));
+    if (!h->act_items.empty())
+        IFD_HIP(hipMemcpyAsync(h->d_act_items, h->act_items.data(), h->act_items.size() * sizeof(StripItem),
+                               hipMemcpyHostToDevice, h->stream));
+    IFD_HIP(hipMemcpyAsync(h->d_unit_first, h->unit_first.data(), h->n_cav * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+    IFD_HIP(hipMemcpyAsync(h->d_unit_count, h->unit_count.data(), h->n_cav * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+    IFD_HIP(hipMemcpyAsync(h->d_desc, h->desc.data(), h->n_cav * sizeof(CavityDesc), hipMemcpyHostToDevice, h->stream));
+    // the host vectors may change before the copies run
+    IFD_HIP(hipStreamSynchronize(h->stream));
+    h->graph_dirty = true;
+    return IFDLBM_OK;
+}
+
+StepArgs step_args(ifdlbm_s* h)
+{
+    StepArgs a{};
+    a.f_in = h->d_f[h->cur];
+    a.f_out = h->d_f[h->cur ^ 1];
+    a.l_in = h->d_l[h->cur];
+    a.l_out = h->d_l[h->cur ^ 1];
+    a.desc = h->d_desc;
+    a.geo = h->d_geo;
+    a.geo32 = h->d_geo32;
+    a.partial = h->d_partial;
+    a.hat_plus = h->d_hp;
+    a.bar_plus = h->d_bp;
+    a.bar_half = h->d_fb;
+    a.lam_new = h->d_ln;
+    return a;
+}
+
+// Enqueue one time step of the running cavities, reading buffer `cur`.
+int enqueue_step(ifdlbm_s* h, bool residual)
+{
+    const StepArgs a = step_args(h);
+    const int prec = h->opt.precision;
+    const bool staged = h->opt.kernel == IFDLBM_KERNEL_STAGED;
+    hipError_t e = hipSuccess;
+    if (h->opt.batched) {
+        e = staged ? launch_staged_step(prec, a, h->d_act_blocks, 0, (int)h->act_blocks.size(), residual, h->stream)
+                   : launch_fused_step(prec, a, h->d_act_items, 0, (int)h->act_items.size(), residual, h->stream);
+    } else {
+        for (int c = 0; c < h->n_cav && e == hipSuccess; ++c) {
+            if (!h->unit_count[c]) continue;
+            e = staged ? launch_staged_step(prec, a, h->d_act_blocks, h->unit_first[c], h->unit_count[c], residual, h->stream)
+                       : launch_fused_step(prec, a, h->d_act_items, h->unit_first[c], h->unit_count[c], residual, h->stream);
+        }
+    }
+    if (e == hipSuccess && residual)
+        e = launch_reduce_partials(h->d_partial, h->d_unit_first, h->d_unit_count, h->n_cav, h->d_res, h->stream);
+    if (e != hipSuccess) return fail(IFDLBM_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
+    return IFDLBM_OK;
+}
+
+bool is_residual_step(const ifdlbm_s* h, int64_t step_index) { return (step_index + 1) % h->opt.residual_every == 0; }
+
+int eager_steps(ifdlbm_s* h, int64_t n)
+{
+    for (int64_t s = 0; s < n; ++s) {
+        int rc = enqueue_step(h, is_residual_step(h, h->step_count));
+        if (rc) return rc;
+        h->cur ^= 1;
+        h->step_count++;
+    }
+    return IFDLBM_OK;
+}
+
+// Capture graph_steps steps starting at a step index that is a multiple of
+// graph_steps (graph_steps is even and a multiple of residual_every, so every
+// replay starts from the same buffer and has the same residual pattern).
+int build_graph(ifdlbm_s* h)
+{
+    if (h->graph_exec) {
+        IFD_HIP(hipGraphExecDestroy(h->graph_exec));
+        h->graph_exec = nullptr;
+    }
+    const int G = h->opt.graph_steps;
+    const int cur0 = h->cur;
+    const int64_t count0 = h->step_count;
+    hipGraph_t graph = nullptr;
+    IFD_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    int rc = IFDLBM_OK;
+    for (int s = 0; s < G && rc == IFDLBM_OK; ++s) {
+        rc = enqueue_step(h, is_residual_step(h, s));
+        h->cur ^= 1;
+    }
+    hipError_t e = hipStreamEndCapture(h->stream, &graph);
+    h->cur = cur0;
+    h->step_count = count0;
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(IFDLBM_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&h->graph_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(IFDLBM_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    h->graph_dirty = false;
+    return IFDLBM_OK;
+}
+
+int do_steps(ifdlbm_s* h, int64_t n)
+{
+    const int G = h->opt.graph_steps;
+    if (G <= 0) return eager_steps(h, n);
+    int64_t lead = (G - h->step_count % G) % G;
+    lead = std::min(lead, n);
+    int rc = eager_steps(h, lead);
+    if (rc) return rc;
+    n -= lead;
+    if (n >= G && h->graph_dirty) {
+        rc = build_graph(h);
+        if (rc) return rc;
+    }
+    while (n >= G) {
+        IFD_HIP(hipGraphLaunch(h->graph_exec, h->stream));
+        h->step_count += G;   // G is even: the current buffer is unchanged
+        n -= G;
+    }
+    return eager_steps(h, n);
+}
+
+// Copy cavity c's current state into the other buffer too, so that it no
+// longer matters which buffer is current once the cavity stops stepping.
+int mirror_state(ifdlbm_s* h, int c)
+{
+    const CavityDesc& d = h->desc[c];
+    const int prec = h->opt.precision;
+    const size_t fb = f_elem_size(prec), lb = l_elem_size(prec);
+    char* f0 = static_cast<char*>(h->d_f[h->cur]);
+    char* f1 = static_cast<char*>(h->d_f[h->cur ^ 1]);
+    char* l0 = static_cast<char*>(h->d_l[h->cur]);
+    char* l1 = static_cast<char*>(h->d_l[h->cur ^ 1]);
+    IFD_HIP(hipMemcpyAsync(f1 + d.f_off * fb, f0 + d.f_off * fb, 9 * d.plane * fb, hipMemcpyDeviceToDevice, h->stream));
+    IFD_HIP(hipMemcpyAsync(l1 + d.l_off * lb, l0 + d.l_off * lb, d.plane * lb, hipMemcpyDeviceToDevice, h->stream));
+    return IFDLBM_OK;
+}
+
+int check_cav(const ifdlbm_s* h, int32_t c)
+{
+    if (!h) return fail(IFDLBM_EINVAL, "null handle");
+    if (c < 0 || c >= h->n_cav) return fail(IFDLBM_EINVAL, "cavity index out of range");
+    return IFDLBM_OK;
+}
+
+int read_residuals(ifdlbm_s* h, std::vector<double>& sums)
+{
+    sums.assign((size_t)h->n_cav * kPartials, 0.0);
+    IFD_HIP(hipMemcpyAsync(sums.data(), h->d_res, sums.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    IFD_HIP(hipStreamSynchronize(h->stream));
+    return IFDLBM_OK;
+}
+
+double rel(double num2, double den2) { return num2 <= 0.0 ? 0.0 : std::sqrt(num2) / std::sqrt(den2); }
+
+// Eq. (2.19) from the partial sums of one cavity of nn nodes: E(u), and E(P)
+// of the pressure with its spatial mean removed (sum (dP - mean dP)^2 =
+// sum dP^2 - (sum dP)^2 / nn, likewise for P).  Returns false if non-finite.
+bool residuals_of(const double* s, double nn, double& eu, double& ep)
+{
+    eu = rel(s[0], s[1]);
+    ep = rel(s[2] - s[4] * s[4] / nn, s[3] - s[5] * s[5] / nn);
+    return s[6] == 0.0 && std::isfinite(eu) && std::isfinite(ep);
+}
+
+void free_all(ifdlbm_s* h)
+{
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    void* ptrs[] = {h->d_f[0], h->d_f[1], h->d_l[0], h->d_l[1], h->d_desc, h->d_geo, h->d_geo32, h->d_hp, h->d_bp,
+                    h->d_fb, h->d_ln, h->d_all_blocks, h->d_act_blocks, h->d_act_items, h->d_unit_first,
+                    h->d_unit_count, h->d_partial, h->d_res, h->d_scratch};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+}
+
+template <typename P>
+int dalloc(P** p, size_t bytes)
+{
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(p), std::max<size_t>(bytes, 256));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(e == hipErrorOutOfMemory ? IFDLBM_ENOMEM : IFDLBM_EDEVICE,
+                    std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+    }
+    return IFDLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ifdlbm_default_options(ifdlbm_options* opt)
+{
+    if (!opt) return fail(IFDLBM_EINVAL, "null options");
+    std::memset(opt, 0, sizeof(*opt));
+    opt->precision = IFDLBM_FP64;
+    opt->cfl = 0.5;
+    opt->mix = 0.5;
+    opt->rho0 = 1.0;
+    opt->gamma_min = 1e-6;
+    opt->residual_every = 1;
+    opt->kernel = IFDLBM_KERNEL_STAGED;
+    opt->batched = 1;
+    opt->graph_steps = 0;
+    opt->hip_stream = nullptr;
+    return IFDLBM_OK;
+}
+
+int ifdlbm_create(const ifdlbm_cavity* cav, int32_t n_cav, const ifdlbm_options* opt, ifdlbm_t** out)
+{
+    if (!out) return fail(IFDLBM_EINVAL, "null output handle pointer");
+    *out = nullptr;
+    if (!cav || !opt || n_cav <= 0) return fail(IFDLBM_EINVAL, "need at least one cavity and options");
+    const ifdlbm_options& o = *opt;
+    if (o.precision < IFDLBM_FP64 || o.precision > IFDLBM_FP16DEV) return fail(IFDLBM_EINVAL, "unknown precision");
+    if (!(o.cfl > 0.0) || !(o.mix >= 0.0 && o.mix <= 1.0) || !(o.gamma_min > 0.0) || !std::isfinite(o.rho0))
+        return fail(IFDLBM_EINVAL, "cfl must be > 0, mix in [0, 1], gamma_min > 0, rho0 finite");
+    if (o.residual_every < 1) return fail(IFDLBM_EINVAL, "residual_every must be >= 1");
+    if (o.kernel != IFDLBM_KERNEL_FUSED && o.kernel != IFDLBM_KERNEL_STAGED) return fail(IFDLBM_EINVAL, "unknown kernel");
+    if (o.graph_steps < 0 || (o.graph_steps > 0 && (o.graph_steps % 2 != 0 || o.graph_steps % o.residual_every != 0)))
+        return fail(IFDLBM_EINVAL, "graph_steps must be 0, or even and a multiple of residual_every");
+    for (int c = 0; c < n_cav; ++c) {
+        const ifdlbm_cavity& v = cav[c];
+        const std::string id = "cavity " + std::to_string(c) + ": ";
+        if (v.n_xi < 5 || v.n_eta < 5) return fail(IFDLBM_EINVAL, id + "n_xi and n_eta must be >= 5");
+        if (v.n_xi > 32767 || (int64_t)v.n_xi * v.n_eta > (int64_t)1 << 30)
+            return fail(IFDLBM_EINVAL, id + "grid too large (n_xi <= 32767, n_xi * n_eta <= 2^30)");
+        if (!(v.theta_deg > 0.0 && v.theta_deg <= 90.0)) return fail(IFDLBM_EINVAL, id + "theta_deg must be in (0, 90]");
+        if (!(v.n > 0.0) || !std::isfinite(v.n)) return fail(IFDLBM_EINVAL, id + "n must be > 0");
+        if (!(v.re > 0.0) || !std::isfinite(v.re)) return fail(IFDLBM_EINVAL, id + "re must be > 0");
+        if (!(v.u_lid != 0.0) || !std::isfinite(v.u_lid)) return fail(IFDLBM_EINVAL, id + "u_lid must be nonzero");
+    }
+
+    ifdlbm_s* h = new (std::nothrow) ifdlbm_s();
+    if (!h) return fail(IFDLBM_ENOMEM, "handle allocation");
+    h->n_cav = n_cav;
+    h->opt = o;
+    h->cav.assign(cav, cav + n_cav);
+    h->desc.resize(n_cav);
+    h->status.assign(n_cav, IFDLBM_STATUS_RUNNING);
+    h->res_u.assign(n_cav, NAN);
+    h->res_p.assign(n_cav, NAN);
+    h->unit_first.assign(n_cav, 0);
+    h->unit_count.assign(n_cav, 0);
+
+    int rc = IFDLBM_OK;
+    auto bail = [&](int code) {
+        free_all(h);
+        delete h;
+        return code;
+    };
+    if (o.hip_stream) {
+        h->stream = static_cast<hipStream_t>(o.hip_stream);
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return bail(fail(IFDLBM_EDEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e)));
+        h->own_stream = true;
+    }
+
+    // layout and FP64 metric terms (Eqs. 3.2-3.8.2)
+    std::vector<double> geo;
+    int64_t f_off = 0, l_off = 0, max_nodes = 0;
+    size_t n_items = 0, n_blocks = 0;
+    for (int c = 0; c < n_cav; ++c) {
+        const ifdlbm_cavity& v = cav[c];
+        CavityDesc& d = h->desc[c];
+        std::memset(&d, 0, sizeof(d));
+        d.nx = v.n_xi;
+        d.ny = v.n_eta;
+        d.pitch = (v.n_xi + 15) / 16 * 16;
+        d.active = 1;
+        d.plane = (int64_t)d.ny * d.pitch;
+        d.f_off = f_off;
+        d.l_off = l_off;
+        f_off += 9 * d.plane;
+        l_off += d.plane;
+        d.geo_off = (int64_t)geo.size();
+        d.dxi = 1.0 / (v.n_xi - 1);
+        d.deta = 1.0 / (v.n_eta - 1);
+        d.cot = cot_deg(v.theta_deg);
+        for (int j = 0; j < d.ny; ++j) geo.push_back(1.0 / (1.0 + 2.0 * d.cot * (j * d.deta)));   // a_j = 1/J
+        for (int i = 0; i < d.nx; ++i) geo.push_back(d.cot * (double)(2 * i - (d.nx - 1)) / (double)(d.nx - 1));   // s_i = x_eta
+        const double U = std::fabs(v.u_lid);
+        d.dt = o.cfl * std::min(d.dxi, d.deta);
+        d.K = std::pow(U, 2.0 - v.n) / v.re;   // Eq. (2.15.1), L = 1
+        d.expo = 0.5 * (v.n - 1.0);
+        d.g2min = o.gamma_min * o.gamma_min;
+        d.mix = o.mix;
+        d.u_lid = v.u_lid;
+        d.inv2dxi = 0.5 / d.dxi;
+        d.inv2deta = 0.5 / d.deta;
+        d.lam_newton = d.K / kCs2;
+        d.lam0 = U / (v.re * kCs2);
+        d.newtonian = v.n == 1.0;
+        d.index = c;
+        const int64_t nn = (int64_t)d.nx * d.ny;
+        max_nodes = std::max(max_nodes, nn);
+        n_blocks += (size_t)((nn + kNodeBlock - 1) / kNodeBlock);
+        n_items += (size_t)ceil_div(d.ny, kSegRows) * ceil_div(d.nx, kStripOut);
+        for (int n = 0; n < nn; n += kNodeBlock) h->all_blocks.push_back({c, n});
+    }
+    h->f_elems = (size_t)f_off;
+    h->l_elems = (size_t)l_off;
+    h->max_units = o.kernel == IFDLBM_KERNEL_STAGED ? n_blocks : n_items;
+    h->scratch_elems = (size_t)max_nodes * 10;
+
+    const int prec = o.precision;
+    const size_t fs = f_elem_size(prec), ls = l_elem_size(prec), ts = t_elem_size(prec);
+    for (int b = 0; b < 2 && !rc; ++b) {
+        rc = dalloc(&h->d_f[b], h->f_elems * fs);
+        if (!rc) rc = dalloc(&h->d_l[b], h->l_elems * ls);
+    }
+    if (!rc) rc = dalloc(&h->d_desc, n_cav * sizeof(CavityDesc));
+    if (!rc) rc = dalloc(&h->d_geo, geo.size() * sizeof(double));
+    if (!rc) rc = dalloc(&h->d_geo32, geo.size() * sizeof(float));
+    if (!rc && o.kernel == IFDLBM_KERNEL_STAGED) {
+        rc = dalloc(&h->d_hp, h->f_elems * ts);
+        if (!rc) rc = dalloc(&h->d_bp, h->f_elems * ts);
+        if (!rc) rc = dalloc(&h->d_fb, h->f_elems * ts);
+        if (!rc) rc = dalloc(&h->d_ln, h->l_elems * ts);
+    }
+    if (!rc) rc = dalloc(&h->d_all_blocks, h->all_blocks.size() * sizeof(NodeBlock));
+    if (!rc) rc = dalloc(&h->d_act_blocks, n_blocks * sizeof(NodeBlock));
+    if (!rc) rc = dalloc(&h->d_act_items, n_items * sizeof(StripItem));
+    if (!rc) rc = dalloc(&h->d_unit_first, n_cav * sizeof(int32_t));
+    if (!rc) rc = dalloc(&h->d_unit_count, n_cav * sizeof(int32_t));
+    if (!rc) rc = dalloc(&h->d_partial, h->max_units * kPartials * sizeof(double));
+    if (!rc) rc = dalloc(&h->d_res, (size_t)n_cav * kPartials * sizeof(double));
+    if (!rc) rc = dalloc(&h->d_scratch, h->scratch_elems * sizeof(double));
+    if (rc) return bail(rc);
+
+    std::vector<float> geo32(geo.begin(), geo.end());
+    auto copy = [&](void* dst, const void* src, size_t bytes) {
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream);
+    };
+    hipError_t e = copy(h->d_geo, geo.data(), geo.size() * sizeof(double));
+    if (e == hipSuccess) e = copy(h->d_geo32, geo32.data(), geo32.size() * sizeof(float));
+    if (e == hipSuccess) e = copy(h->d_all_blocks, h->all_blocks.data(), h->all_blocks.size() * sizeof(NodeBlock));
+    if (e == hipSuccess) e = copy(h->d_desc, h->desc.data(), n_cav * sizeof(CavityDesc));
+    if (e == hipSuccess) e = hipMemsetAsync(h->d_res, 0, (size_t)n_cav * kPartials * sizeof(double), h->stream);
+    if (e == hipSuccess)
+        e = launch_init(prec, h->d_f[0], h->d_l[0], h->d_desc, h->d_all_blocks, (int)h->all_blocks.size(), h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return bail(fail(IFDLBM_EDEVICE, std::string("create: ") + hipGetErrorString(e)));
+    rc = rebuild_worklists(h);
+    if (rc) return bail(rc);
+    *out = h;
+    return IFDLBM_OK;
+}
+
+int ifdlbm_step(ifdlbm_t* h, int64_t n_steps)
+{
+    if (!h) return fail(IFDLBM_EINVAL, "null handle");
+    if (n_steps < 0) return fail(IFDLBM_EINVAL, "n_steps must be >= 0");
+    return do_steps(h, n_steps);
+}
+
+int ifdlbm_sync(ifdlbm_t* h)
+{
+    if (!h) return fail(IFDLBM_EINVAL, "null handle");
+    IFD_HIP(hipStreamSynchronize(h->stream));
+    return IFDLBM_OK;
+}
+
+int ifdlbm_get_residuals(ifdlbm_t* h, double* res_u, double* res_p)
+{
+    if (!h) return fail(IFDLBM_EINVAL, "null handle");
+    std::vector<double> sums;
+    int rc = read_residuals(h, sums);
+    if (rc) return rc;
+    for (int c = 0; c < h->n_cav; ++c) {
+        if (h->desc[c].active) {
+            double eu, ep;
+            const bool ok = residuals_of(&sums[(size_t)c * kPartials], (double)h->desc[c].nx * h->desc[c].ny, eu, ep);
+            h->res_u[c] = ok ? eu : NAN;
+            h->res_p[c] = ok ? ep : NAN;
+        }
+        if (res_u) res_u[c] = h->res_u[c];
+        if (res_p) res_p[c] = h->res_p[c];
+    }
+    return IFDLBM_OK;
+}
+
+int ifdlbm_run_to_steady(ifdlbm_t* h, double tol, int64_t max_steps, int64_t* steps_done, double* res_u, double* res_p)
+{
+    if (!h) return fail(IFDLBM_EINVAL, "null handle");
+    if (!(tol >= 0.0) || max_steps < 0) return fail(IFDLBM_EINVAL, "tol must be >= 0 and max_steps >= 0");
+    std::vector<int64_t> done(h->n_cav, 0);
+    bool diverged = false;
+    int64_t taken = 0;
+    std::vector<double> sums;
+    auto any_active = [&]() {
+        for (int c = 0; c < h->n_cav; ++c)
+            if (h->desc[c].active) return true;
+        return false;
+    };
+    while (any_active() && taken < max_steps) {
+        const int R = h->opt.residual_every;
+        int64_t n = R - h->step_count % R;   // steps up to and including the next residual step
+        n = std::min(n, max_steps - taken);
+        int rc = do_steps(h, n);
+        if (rc) return rc;
+        taken += n;
+        for (int c = 0; c < h->n_cav; ++c)
+            if (h->desc[c].active) done[c] += n;
+        if (h->step_count % R != 0) break;   // max_steps ended between residual steps
+        rc = read_residuals(h, sums);
+        if (rc) return rc;
+        bool changed = false;
+        for (int c = 0; c < h->n_cav; ++c) {
+            if (!h->desc[c].active) continue;
+            double eu, ep;
+            const bool ok = residuals_of(&sums[(size_t)c * kPartials], (double)h->desc[c].nx * h->desc[c].ny, eu, ep);
+            h->res_u[c] = ok ? eu : NAN;
+            h->res_p[c] = ok ? ep : NAN;
+            int st = IFDLBM_STATUS_RUNNING;
+            if (!ok)
+                st = IFDLBM_STATUS_DIVERGED;
+            else if (eu <= tol && ep <= tol)
+                st = IFDLBM_STATUS_CONVERGED;
+            if (st != IFDLBM_STATUS_RUNNING) {
+                h->status[c] = st;
+                diverged |= st == IFDLBM_STATUS_DIVERGED;
+                h->desc[c].active = 0;
+                rc = mirror_state(h, c);
+                if (rc) return rc;
+                changed = true;
+            }
+        }
+        if (changed) {
+            rc = rebuild_worklists(h);
+            if (rc) return rc;
+        }
+    }
+    bool unconverged = false;
+    for (int c = 0; c < h->n_cav; ++c) {
+        if (h->desc[c].active) {
+            h->status[c] = IFDLBM_STATUS_NOT_CONVERGED;
+            unconverged = true;
+        }
+        if (steps_done) steps_done[c] = done[c];
+        if (res_u) res_u[c] = h->res_u[c];
+        if (res_p) res_p[c] = h->res_p[c];
+    }
+    IFD_HIP(hipStreamSynchronize(h->stream));
+    if (diverged) return fail(IFDLBM_EDIVERGED, "a cavity diverged");
+    if (unconverged) return fail(IFDLBM_ENOTCONVERGED, "max_steps reached before tol");
+    return IFDLBM_OK;
+}
+
+int ifdlbm_get_fields_device(ifdlbm_t* h, int32_t cav, void* u, void* v, void* p, int32_t dtype)
+{
+    int rc = check_cav(h, cav);
+    if (rc) return rc;
+    if (dtype != 0 && dtype != 1) return fail(IFDLBM_EINVAL, "dtype must be 0 (float64) or 1 (float32)");
+    hipError_t e = launch_fields(h->opt.precision, h->d_f[h->cur], h->d_desc, cav, h->desc[cav], u, v, p, dtype, h->stream);
+    if (e != hipSuccess) return fail(IFDLBM_EDEVICE, std::string("fields: ") + hipGetErrorString(e));
+    return IFDLBM_OK;
+}
+
+int ifdlbm_get_fields(ifdlbm_t* h, int32_t cav, double* u, double* v, double* p)
+{
+    int rc = check_cav(h, cav);
+    if (rc) return rc;
+    const CavityDesc& d = h->desc[cav];
+    const size_t nn = (size_t)d.nx * d.ny;
+    double* s = h->d_scratch;
+    rc = ifdlbm_get_fields_device(h, cav, s, s + nn, s + 2 * nn, 0);
+    if (rc) return rc;
+    double* outs[3] = {u, v, p};
+    for (int q = 0; q < 3; ++q)
+        if (outs[q]) IFD_HIP(hipMemcpyAsync(outs[q], s + q * nn, nn * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    IFD_HIP(hipStreamSynchronize(h->stream));
+    return IFDLBM_OK;
+}
+
+int ifdlbm_kinetic_energy(ifdlbm_t* h, int32_t cav, double* energy)
+{
+    int rc = check_cav(h, cav);
+    if (rc) return rc;
+    if (!energy) return fail(IFDLBM_EINVAL, "null energy pointer");
+    const CavityDesc& d = h->desc[cav];
+    const size_t nb = ((size_t)d.nx * d.ny + 255) / 256;
+    hipError_t e = launch_energy(h->opt.precision, h->d_f[h->cur], h->d_desc, h->d_geo, cav, d, h->d_scratch, h->stream);
+    if (e != hipSuccess) return fail(IFDLBM_EDEVICE, std::string("energy: ") + hipGetErrorString(e));
+    std::vector<double> part(nb);
+    IFD_HIP(hipMemcpyAsync(part.data(), h->d_scratch, nb * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    IFD_HIP(hipStreamSynchronize(h->stream));
+    double s = 0.0;
+    for (double x : part) s += x;
+    *energy = s;
+    return IFDLBM_OK;
+}
+
+int ifdlbm_get_state(ifdlbm_t* h, int32_t cav, double* fhat, double* lambda)
+{
+    int rc = check_cav(h, cav);
+    if (rc) return rc;
+    if (!fhat || !lambda) return fail(IFDLBM_EINVAL, "null state array");
+    const CavityDesc& d = h->desc[cav];
+    const size_t nn = (size_t)d.nx * d.ny;
+    double* s = h->d_scratch;
+    hipError_t e = launch_state_out(h->opt.precision, h->d_f[h->cur], h->d_l[h->cur], d, h->opt.rho0, s, s + 9 * nn, h->stream);
+    if (e != hipSuccess) return fail(IFDLBM_EDEVICE, std::string("state out: ") + hipGetErrorString(e));
+    IFD_HIP(hipMemcpyAsync(fhat, s, 9 * nn * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    IFD_HIP(hipMemcpyAsync(lambda, s + 9 * nn, nn * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    IFD_HIP(hipStreamSynchronize(h->stream));
+    return IFDLBM_OK;
+}
+
+int ifdlbm_set_state(ifdlbm_t* h, int32_t cav, const double* fhat, const double* lambda)
+{
+    int rc = check_cav(h, cav);
+    if (rc) return rc;
+    if (!fhat || !lambda) return fail(IFDLBM_EINVAL, "null state array");
+    const CavityDesc& d = h->desc[cav];
+    const size_t nn = (size_t)d.nx * d.ny;
+    double* s = h->d_scratch;
+    IFD_HIP(hipMemcpyAsync(s, fhat, 9 * nn * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    IFD_HIP(hipMemcpyAsync(s + 9 * nn, lambda, nn * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    for (int b = 0; b < 2; ++b) {
+        hipError_t e = launch_state_in(h->opt.precision, h->d_f[b], h->d_l[b], d, h->opt.rho0, s, s + 9 * nn, h->stream);
+        if (e != hipSuccess) return fail(IFDLBM_EDEVICE, std::string("state in: ") + hipGetErrorString(e));
+    }
+    IFD_HIP(hipStreamSynchronize(h->stream));
+    h->status[cav] = IFDLBM_STATUS_RUNNING;
+    if (!h->desc[cav].active) {
+        h->desc[cav].active = 1;
+        rc = rebuild_worklists(h);
+        if (rc) return rc;
+    }
+    return IFDLBM_OK;
+}
+
+int ifdlbm_status(ifdlbm_t* h, int32_t cav)
+{
+    int rc = check_cav(h, cav);
+    if (rc) return rc;
+    return h->status[cav];
+}
+
+int ifdlbm_info(ifdlbm_t* h, ifdlbm_info_t* info)
+{
+    if (!h || !info) return fail(IFDLBM_EINVAL, "null argument");
+    std::memset(info, 0, sizeof(*info));
+    info->n_cavities = h->n_cav;
+    for (int c = 0; c < h->n_cav; ++c)
+        if (h->desc[c].active) {
+            info->n_active++;
+            info->nodes += (int64_t)h->desc[c].nx * h->desc[c].ny;
+        }
+    const int prec = h->opt.precision;
+    info->state_bytes = (int64_t)(h->f_elems * f_elem_size(prec) + h->l_elems * l_elem_size(prec));
+    info->alg_bytes_per_node = 2.0 * (9.0 * f_elem_size(prec) + l_elem_size(prec));
+    int launches = units_per_step(h);
+    if (!h->opt.batched) launches *= info->n_active;
+    info->launches_per_step = launches;
+    info->work_items = h->opt.kernel == IFDLBM_KERNEL_STAGED ? (int64_t)h->act_blocks.size() : (int64_t)h->act_items.size();
+    return IFDLBM_OK;
+}
+
+void ifdlbm_destroy(ifdlbm_t* h)
+{
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    free_all(h);
+    delete h;
+}
+
+const char* ifdlbm_strerror(int code)
+{
+    switch (code) {
+    case IFDLBM_OK: return "ok";
+    case IFDLBM_EINVAL: return "invalid argument";
+    case IFDLBM_ENOMEM: return "out of memory";
+    case IFDLBM_EDEVICE: return "HIP device error";
+    case IFDLBM_EDIVERGED: return "a cavity diverged";
+    case IFDLBM_ENOTCONVERGED: return "not converged within max_steps";
+    }
+    return "unknown error code";
+}
+
+const char* ifdlbm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

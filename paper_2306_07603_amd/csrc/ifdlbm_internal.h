@@ -1,0 +1,88 @@
+// ifdlbm_internal.h -- launch interface between the C-ABI host code and the
+// kernels of libifdlbm.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_device.h"
+
+namespace ifd {
+
+// A block of 256 consecutive nodes (in [j][i] order) of one cavity: the work
+// unit of the per-node kernels (initialisation, staged step, residual, output).
+struct NodeBlock {
+    int32_t cav;     // index into the descriptor table
+    int32_t first;   // first node, j * nx + i
+};
+constexpr int kNodeBlock = 256;
+
+// A wavefront work item of the fused step: output columns [i0, i1) and output
+// rows [j0, j1) of one cavity.  The 64 lanes cover columns [i0 - 4, i0 + 60),
+// so i1 - i0 <= kStripOut.  Strips and row segments split a cavity evenly and
+// hold at least two columns and rows, so a wall node and its inward
+// neighbour always belong to the same item.
+constexpr int kStripOut = 56;
+constexpr int kWaveLanes = 64;
+constexpr int kHaloCols = 4;
+struct StripItem {
+    int32_t cav;
+    int16_t i0, i1;
+    int32_t j0, j1;
+};
+
+// Residual partial sums of Eq. (2.19) per work unit: sum |u_new - u_old|^2,
+// sum |u_new|^2, sum (P_new - P_old)^2, sum P_new^2, sum (P_new - P_old),
+// sum P_new, count of non-finite nodes.  The two plain sums give E(P) of the
+// pressure with its spatial mean removed.
+constexpr int kPartials = 7;
+
+struct StepArgs {
+    const void* f_in;        // distributions, storage type, step start
+    void* f_out;             // distributions, storage type, step end
+    const void* l_in;        // lambda, step start
+    void* l_out;             // lambda, step end
+    const CavityDesc* desc;  // per-cavity descriptors
+    const double* geo;       // metric tables a_j, s_i (FP64)
+    const float* geo32;      // the same tables rounded to FP32
+    double* partial;         // residual partials, kPartials per work unit
+    // staged schedule only: temporaries in the arithmetic type
+    void* hat_plus;          // f-hat+ (Eq. 2.15), 9 planes
+    void* bar_plus;          // f-bar+ (Eq. 2.16), then f(t + dt/2) (Eq. 2.17), 9 planes
+    void* bar_half;          // f-bar(t + dt/2) (Eq. 3.7), 9 planes
+    void* lam_new;           // lambda of this step
+};
+
+// Staged schedule: five launches per step over the node blocks
+// [b0, b0 + nb), plus the residual launch when `residual` is set.
+hipError_t launch_staged_step(int prec, const StepArgs& a, const NodeBlock* blocks, int b0, int nb,
+                              bool residual, hipStream_t s);
+
+// Fused schedule: one launch over the strip items [w0, w0 + nw).
+hipError_t launch_fused_step(int prec, const StepArgs& a, const StripItem* items, int w0, int nw,
+                             bool residual, hipStream_t s);
+
+// Step (1) on every node of the listed blocks.
+hipError_t launch_init(int prec, void* f, void* l, const CavityDesc* desc, const NodeBlock* blocks, int nb,
+                       hipStream_t s);
+
+// Per-cavity deterministic reduction of residual partials:
+// out[c * kPartials + q] = sum over units [first[c], first[c] + count[c]).
+hipError_t launch_reduce_partials(const double* partial, const int32_t* first, const int32_t* count, int n_cav,
+                                  double* out, hipStream_t s);
+
+// u, v, P (FP64 or FP32 by dtype) of one cavity, [j][i] packed.
+hipError_t launch_fields(int prec, const void* f, const CavityDesc* desc, int cav_index, const CavityDesc& hd,
+                         void* u, void* v, void* p, int dtype, hipStream_t s);
+
+// f-hat (rho0 included, FP64, [k][j][i] packed) and lambda of one cavity to / from the state.
+hipError_t launch_state_out(int prec, const void* f, const void* l, const CavityDesc& hd, double rho0,
+                            double* fhat, double* lam, hipStream_t s);
+hipError_t launch_state_in(int prec, void* f, void* l, const CavityDesc& hd, double rho0,
+                           const double* fhat, const double* lam, hipStream_t s);
+
+// Kinetic energy of Eq. (5.1) summed per block, reduced on the host in order.
+hipError_t launch_energy(int prec, const void* f, const CavityDesc* desc, const double* geo, int cav_index,
+                         const CavityDesc& hd, double* partial, hipStream_t s);
+
+}  // namespace ifd

@@ -1,0 +1,219 @@
+// kernels_common.hip -- per-node kernels around the time step: Step (1)
+// initialisation, the residual reduction of Eq. (2.19), macroscopic output
+// (Eqs. 2.10-2.11), checkpoint conversion and the kinetic energy of Eq. (5.1).
+#include "ifdlbm_internal.h"
+
+namespace ifd {
+namespace {
+
+// Step (1): u = 0 and P = 0, except u = (u_lid, 0) on the top row (lid corners
+// included), f-hat = f_eq(P, u), lambda = lambda_0.
+template <int PREC>
+__global__ __launch_bounds__(kNodeBlock) void k_init(void* fv, void* lv, const CavityDesc* desc, const NodeBlock* blocks)
+{
+    using S = Storage<PREC>;
+    using T = typename S::T;
+    const NodeBlock nb = blocks[blockIdx.x];
+    const CavityDesc c = desc[nb.cav];
+    const int n = nb.first + (int)threadIdx.x;
+    if (n >= c.nx * c.ny) return;
+    const int j = n / c.nx, i = n - j * c.nx;
+    const int64_t id = (int64_t)j * c.pitch + i;
+    T e[9];
+    equilibrium(T(0), j == c.ny - 1 ? T(c.u_lid) : T(0), T(0), e);
+    auto* f = static_cast<typename S::F*>(fv);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) S::store(f, c.f_off + k * c.plane + id, k, e[k]);
+    static_cast<typename S::L*>(lv)[c.l_off + id] = T(c.lam0);
+}
+
+// out[c][q] = sum of partial[u][q] over the units of cavity c, in a fixed order.
+__global__ __launch_bounds__(256) void k_reduce(const double* partial, const int32_t* first, const int32_t* count, double* out)
+{
+    __shared__ double sh[kPartials][256];
+    const int c = blockIdx.x;
+    double v[kPartials] = {0, 0, 0, 0, 0, 0, 0};
+    for (int u = threadIdx.x; u < count[c]; u += 256)
+#pragma unroll
+        for (int q = 0; q < kPartials; ++q) v[q] += partial[(int64_t)(first[c] + u) * kPartials + q];
+#pragma unroll
+    for (int q = 0; q < kPartials; ++q) sh[q][threadIdx.x] = v[q];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int q = 0; q < kPartials; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < kPartials) out[(int64_t)c * kPartials + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+template <int PREC, typename O>
+__global__ __launch_bounds__(256) void k_fields(const void* fv, CavityDesc c, O* u, O* v, O* p)
+{
+    using S = Storage<PREC>;
+    using T = typename S::T;
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    if (n >= c.nx * c.ny) return;
+    const int j = n / c.nx, i = n - j * c.nx;
+    const int64_t id = (int64_t)j * c.pitch + i;
+    const auto* f = static_cast<const typename S::F*>(fv);
+    T g[9], P, ux, uy;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) g[k] = S::load(f, c.f_off + k * c.plane + id, k);
+    moments(g, P, ux, uy);
+    if (u) u[n] = (O)ux;
+    if (v) v[n] = (O)uy;
+    if (p) p[n] = (O)P;
+}
+
+__host__ __device__ constexpr double weight(int k) { return k == 0 ? 4.0 / 9.0 : (k < 5 ? 1.0 / 9.0 : 1.0 / 36.0); }
+
+template <int PREC>
+__global__ __launch_bounds__(256) void k_state_out(const void* fv, const void* lv, CavityDesc c, double rho0, double* fhat,
+                                                   double* lam)
+{
+    using S = Storage<PREC>;
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    const int nn = c.nx * c.ny;
+    if (n >= nn) return;
+    const int j = n / c.nx, i = n - j * c.nx;
+    const int64_t id = (int64_t)j * c.pitch + i;
+    const auto* f = static_cast<const typename S::F*>(fv);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) fhat[(int64_t)k * nn + n] = (double)S::load(f, c.f_off + k * c.plane + id, k) + weight(k) * rho0;
+    lam[n] = (double)static_cast<const typename S::L*>(lv)[c.l_off + id];
+}
+
+template <int PREC>
+__global__ __launch_bounds__(256) void k_state_in(void* fv, void* lv, CavityDesc c, double rho0, const double* fhat,
+                                                  const double* lam)
+{
+    using S = Storage<PREC>;
+    using T = typename S::T;
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    const int nn = c.nx * c.ny;
+    if (n >= nn) return;
+    const int j = n / c.nx, i = n - j * c.nx;
+    const int64_t id = (int64_t)j * c.pitch + i;
+    auto* f = static_cast<typename S::F*>(fv);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) S::store(f, c.f_off + k * c.plane + id, k, (T)(fhat[(int64_t)k * nn + n] - weight(k) * rho0));
+    static_cast<typename S::L*>(lv)[c.l_off + id] = (typename S::L)lam[n];
+}
+
+// Eq. (5.1) per block of 256 nodes: 1/2 |u|^2 w_i w_j J_j dxi deta, trapezoid
+// weights w (1/2 on the walls) and J = 1 + 2 eta cot(theta).
+template <int PREC>
+__global__ __launch_bounds__(256) void k_energy(const void* fv, CavityDesc c, double* partial)
+{
+    using S = Storage<PREC>;
+    using T = typename S::T;
+    __shared__ double sh[256];
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    double e = 0.0;
+    if (n < c.nx * c.ny) {
+        const int j = n / c.nx, i = n - j * c.nx;
+        const int64_t id = (int64_t)j * c.pitch + i;
+        const auto* f = static_cast<const typename S::F*>(fv);
+        T g[9], P, ux, uy;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) g[k] = S::load(f, c.f_off + k * c.plane + id, k);
+        moments(g, P, ux, uy);
+        const double wi = (i == 0 || i == c.nx - 1) ? 0.5 : 1.0;
+        const double wj = (j == 0 || j == c.ny - 1) ? 0.5 : 1.0;
+        const double J = 1.0 + 2.0 * c.cot * (j * c.deta);
+        e = 0.5 * wi * wj * J * c.dxi * c.deta * ((double)ux * ux + (double)uy * uy);
+    }
+    sh[threadIdx.x] = e;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+inline unsigned blocks_of(const CavityDesc& c) { return (unsigned)((c.nx * c.ny + 255) / 256); }
+
+}  // namespace
+
+hipError_t launch_init(int prec, void* f, void* l, const CavityDesc* desc, const NodeBlock* blocks, int nb, hipStream_t s)
+{
+    if (nb <= 0) return hipSuccess;
+    switch (prec) {
+    case P_FP64: hipLaunchKernelGGL(k_init<P_FP64>, dim3(nb), dim3(kNodeBlock), 0, s, f, l, desc, blocks); break;
+    case P_FP32: hipLaunchKernelGGL(k_init<P_FP32>, dim3(nb), dim3(kNodeBlock), 0, s, f, l, desc, blocks); break;
+    case P_FP16DEV: hipLaunchKernelGGL(k_init<P_FP16DEV>, dim3(nb), dim3(kNodeBlock), 0, s, f, l, desc, blocks); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(const double* partial, const int32_t* first, const int32_t* count, int n_cav, double* out,
+                                  hipStream_t s)
+{
+    if (n_cav <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce, dim3(n_cav), dim3(256), 0, s, partial, first, count, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fields(int prec, const void* f, const CavityDesc*, int, const CavityDesc& hd, void* u, void* v, void* p,
+                         int dtype, hipStream_t s)
+{
+    const dim3 g(blocks_of(hd)), b(256);
+#define IFD_FIELDS(P)                                                                                              \
+    if (dtype == 0)                                                                                                \
+        hipLaunchKernelGGL((k_fields<P, double>), g, b, 0, s, f, hd, (double*)u, (double*)v, (double*)p);      \
+    else                                                                                                           \
+        hipLaunchKernelGGL((k_fields<P, float>), g, b, 0, s, f, hd, (float*)u, (float*)v, (float*)p);
+    switch (prec) {
+    case P_FP64: IFD_FIELDS(P_FP64) break;
+    case P_FP32: IFD_FIELDS(P_FP32) break;
+    case P_FP16DEV: IFD_FIELDS(P_FP16DEV) break;
+    default: return hipErrorInvalidValue;
+    }
+#undef IFD_FIELDS
+    return hipGetLastError();
+}
+
+hipError_t launch_state_out(int prec, const void* f, const void* l, const CavityDesc& hd, double rho0, double* fhat,
+                            double* lam, hipStream_t s)
+{
+    const dim3 g(blocks_of(hd)), b(256);
+    switch (prec) {
+    case P_FP64: hipLaunchKernelGGL(k_state_out<P_FP64>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
+    case P_FP32: hipLaunchKernelGGL(k_state_out<P_FP32>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
+    case P_FP16DEV: hipLaunchKernelGGL(k_state_out<P_FP16DEV>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_state_in(int prec, void* f, void* l, const CavityDesc& hd, double rho0, const double* fhat,
+                           const double* lam, hipStream_t s)
+{
+    const dim3 g(blocks_of(hd)), b(256);
+    switch (prec) {
+    case P_FP64: hipLaunchKernelGGL(k_state_in<P_FP64>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
+    case P_FP32: hipLaunchKernelGGL(k_state_in<P_FP32>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
+    case P_FP16DEV: hipLaunchKernelGGL(k_state_in<P_FP16DEV>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_energy(int prec, const void* f, const CavityDesc*, const double*, int, const CavityDesc& hd,
+                         double* partial, hipStream_t s)
+{
+    const dim3 g(blocks_of(hd)), b(256);
+    switch (prec) {
+    case P_FP64: hipLaunchKernelGGL(k_energy<P_FP64>, g, b, 0, s, f, hd, partial); break;
+    case P_FP32: hipLaunchKernelGGL(k_energy<P_FP32>, g, b, 0, s, f, hd, partial); break;
+    case P_FP16DEV: hipLaunchKernelGGL(k_energy<P_FP16DEV>, g, b, 0, s, f, hd, partial); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace ifd

@@ -1,0 +1,214 @@
+// lbm_device.h -- device-side data layout and per-node arithmetic of the
+// IFDLBM step (arXiv:2306.07603), shared by the fused and staged kernels.
+//
+// State of a node: the nine deviations g_k = f-hat_k - omega_k rho0 of the
+// distribution f-hat (Eq. 2.3) and the relaxation time lambda that produced
+// them (Eq. 2.14).  Working with deviations drops rho0 from every formula
+// (the collision, the difference stencils and the boundary extrapolation are
+// affine with weights summing to one, or linear with weights summing to
+// zero) and keeps FP32 rounding on the O(u, P) part only.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ifd {
+
+enum Precision { P_FP64 = 0, P_FP32 = 1, P_FP16DEV = 2 };
+
+// One cavity in the device tables.  Planes are SoA: population k of node
+// (i, j) lives at f_off + k * plane + j * pitch + i.
+struct CavityDesc {
+    int32_t nx, ny, pitch, active;
+    int64_t f_off;      // element offset of plane 0 in the distribution arrays
+    int64_t plane;      // elements per plane (ny * pitch)
+    int64_t l_off;      // element offset in the lambda arrays
+    int64_t geo_off;    // a_j at geo_off + j (ny entries), s_i at geo_off + ny + i (nx entries)
+    double dt;          // time step
+    double K;           // consistency coefficient, Eq. (2.15.1)
+    double expo;        // (n - 1) / 2, the exponent of Eq. (1.4) on gamma^2
+    double g2min;       // gamma_min^2
+    double mix;         // central weight of Eq. (2.5)
+    double u_lid;       // lid velocity, Eq. (1.5)
+    double inv2dxi;     // 1 / (2 dxi)
+    double inv2deta;    // 1 / (2 deta)
+    double lam_newton;  // K / c_s^2, lambda of the Newtonian case
+    double lam0;        // initial lambda, U L / (Re c_s^2)
+    double cot;         // 1 / tan(theta), exactly 0 at 90 degrees
+    double dxi, deta;   // grid spacings of the computational square
+    int32_t newtonian;  // n == 1 exactly
+    int32_t index;      // cavity index in the handle
+};
+
+// ---------------------------------------------------------------- storage
+
+template <int PREC> struct Storage;
+
+template <> struct Storage<P_FP64> {
+    using F = double;   // distribution element
+    using L = double;   // lambda element
+    using T = double;   // arithmetic
+    __device__ static inline T load(const F* p, int64_t i, int) { return p[i]; }
+    __device__ static inline void store(F* p, int64_t i, int, T v) { p[i] = v; }
+};
+
+template <> struct Storage<P_FP32> {
+    using F = float;
+    using L = float;
+    using T = float;
+    __device__ static inline T load(const F* p, int64_t i, int) { return p[i]; }
+    __device__ static inline void store(F* p, int64_t i, int, T v) { p[i] = v; }
+};
+
+// FP16 storage of g_k / omega_k: the division by the lattice weight puts all
+// nine planes on the same O(3 P + 3 c.u) scale, inside FP16's normal range.
+template <> struct Storage<P_FP16DEV> {
+    using F = __half;
+    using L = float;
+    using T = float;
+    __device__ static inline float w(int k) { return k == 0 ? 4.0f / 9.0f : (k < 5 ? 1.0f / 9.0f : 1.0f / 36.0f); }
+    __device__ static inline float inv_w(int k) { return k == 0 ? 2.25f : (k < 5 ? 9.0f : 36.0f); }
+    __device__ static inline T load(const F* p, int64_t i, int k) { return w(k) * __half2float(p[i]); }
+    __device__ static inline void store(F* p, int64_t i, int k, T v) { p[i] = __float2half_rn(v * inv_w(k)); }
+};
+
+// ----------------------------------------------------------------- lattice
+// Eq. (2.9): c_k = (cx, cy); omega = 4/9, 1/9 (k = 1..4), 1/36 (k = 5..8);
+// omegabar_0 = -5/9, omegabar_k = omega_k otherwise; c_s^2 = 1/3.
+
+__host__ __device__ constexpr int cxk(int k) { return k == 1 || k == 5 || k == 8 ? 1 : (k == 3 || k == 6 || k == 7 ? -1 : 0); }
+__host__ __device__ constexpr int cyk(int k) { return k == 2 || k == 5 || k == 6 ? 1 : (k == 4 || k == 7 || k == 8 ? -1 : 0); }
+
+// Eqs. (2.10)-(2.11) on deviations: u = sum c_k g_k and
+// P = (c_s^2 / omegabar_0) (-sum_{k>0} g_k + omega_0 |u|^2 / (2 c_s^2)) = 0.6 s - 0.4 |u|^2.
+template <typename T>
+__device__ __forceinline__ void moments(const T g[9], T& P, T& ux, T& uy)
+{
+    ux = (g[1] - g[3]) + (g[5] - g[6]) - (g[7] - g[8]);
+    uy = (g[2] - g[4]) + (g[5] + g[6]) - (g[7] + g[8]);
+    const T s = ((g[1] + g[2]) + (g[3] + g[4])) + ((g[5] + g[6]) + (g[7] + g[8]));
+    P = T(0.6) * s - T(0.4) * (ux * ux + uy * uy);
+}
+
+// Eq. (2.8) minus omega_k rho0, with the second-order term over 2 c_s^4:
+// e_0 = -5/3 P - 2/3 |u|^2, e_k = omega_k (3 P + 3 c.u + 4.5 (c.u)^2 - 1.5 |u|^2).
+template <typename T>
+__device__ __forceinline__ void equilibrium(T P, T ux, T uy, T e[9])
+{
+    const T uu = ux * ux + uy * uy;
+    const T base = T(3) * P - T(1.5) * uu;
+    const T w1 = T(1) / T(9), w5 = T(1) / T(36);
+    auto q = [&](T cu) { return base + cu * (T(3) + T(4.5) * cu); };
+    e[0] = T(-5) / T(3) * P - T(2) / T(3) * uu;
+    e[1] = w1 * q(ux);
+    e[2] = w1 * q(uy);
+    e[3] = w1 * q(-ux);
+    e[4] = w1 * q(-uy);
+    e[5] = w5 * q(ux + uy);
+    e[6] = w5 * q(uy - ux);
+    e[7] = w5 * q(-ux - uy);
+    e[8] = w5 * q(ux - uy);
+}
+
+template <typename T> __device__ __forceinline__ T pow_pos(T x, T y);
+template <> __device__ __forceinline__ double pow_pos<double>(double x, double y) { return pow(x, y); }
+template <> __device__ __forceinline__ float pow_pos<float>(float x, float y)
+{
+    // x >= gamma_min^2 > 0 is a normal float: v_log_f32 / v_exp_f32 (base 2)
+    return __builtin_amdgcn_exp2f(y * __builtin_amdgcn_logf(x));
+}
+
+// Step (2): lambda from the non-equilibrium second moment, Eqs. (2.12)-(2.14)
+// and (1.4).  With f from f-hat by Eq. (2.18), f - f_eq = 2 lam_old (g - e) /
+// (2 lam_old + dt), so D = (grad u + grad u^T)/2 = -3 Pi / (2 lam_old + dt)
+// with Pi = sum_k c_k c_k (g_k - e_k), and 2 D:D = 18 (Pxx^2 + 2 Pxy^2 + Pyy^2)
+// / (2 lam_old + dt)^2.  mu = K max(2 D:D, gamma_min^2)^((n-1)/2), lambda = mu / c_s^2.
+template <typename T>
+__device__ __forceinline__ T relaxation_time(const T g[9], const T e[9], T lam_old, const CavityDesc& c)
+{
+    if (c.newtonian) return T(c.lam_newton);
+    T n[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) n[k] = g[k] - e[k];
+    const T s58 = (n[5] + n[6]) + (n[7] + n[8]);
+    const T pxx = (n[1] + n[3]) + s58;
+    const T pyy = (n[2] + n[4]) + s58;
+    const T pxy = (n[5] - n[6]) + (n[7] - n[8]);
+    const T r = T(1) / (T(2) * lam_old + T(c.dt));
+    T gamma2 = T(18) * (pxx * pxx + T(2) * pxy * pxy + pyy * pyy) * r * r;
+    gamma2 = gamma2 > T(c.g2min) ? gamma2 : T(c.g2min);
+    return T(3) * T(c.K) * pow_pos<T>(gamma2, T(c.expo));
+}
+
+// Steps (3)-(4): Eq. (2.15) f-hat+ = ((2 lam - dt) g + 2 dt e) / (2 lam + dt) and
+// Eq. (2.16) f-bar+ = ((4 lam - dt) g + 3 dt e) / (4 lam + 2 dt).
+template <typename T>
+struct Collision {
+    T a_hat, b_hat, a_bar, b_bar;
+    __device__ __forceinline__ Collision(T lam, T dt)
+    {
+        const T r = T(1) / (T(2) * lam + dt);
+        a_hat = (T(2) * lam - dt) * r;
+        b_hat = T(2) * dt * r;
+        a_bar = (T(4) * lam - dt) * (T(0.5) * r);
+        b_bar = T(1.5) * dt * r;
+    }
+};
+
+// Eq. (2.17): f = (4 lam f-bar + dt e) / (4 lam + dt).
+template <typename T>
+struct HalfStep {
+    T a, b;
+    __device__ __forceinline__ HalfStep(T lam, T dt)
+    {
+        const T r = T(1) / (T(4) * lam + dt);
+        a = T(4) * lam * r;
+        b = dt * r;
+    }
+};
+
+// Eq. (2.5) with (2.6)-(2.7): eps * central + (1 - eps) * second-order upwind,
+// times 2h, from the five points m2, m1, c0, p1, p2 along one grid line.  The
+// upwind side follows the sign of the contravariant velocity (c >= 0: points
+// behind).  Where the second upwind point would leave the grid (lo_edge for
+// c >= 0, hi_edge for c < 0) the first-order one-sided difference is used.
+template <typename T>
+__device__ __forceinline__ T mixed_diff_2h(T m2, T m1, T c0, T p1, T p2, bool c_nonneg, bool lo_edge, bool hi_edge, T eps)
+{
+    const T cen = p1 - m1;
+    T up;
+    if (c_nonneg)
+        up = lo_edge ? T(2) * (c0 - m1) : (T(3) * c0 - T(4) * m1) + m2;
+    else
+        up = hi_edge ? T(2) * (p1 - c0) : (T(4) * p1 - T(3) * c0) - p2;
+    return eps * cen + (T(1) - eps) * up;
+}
+
+// Boundary classification and the non-equilibrium extrapolation neighbour
+// (one index inward, diagonal at corners).
+__device__ __forceinline__ bool is_boundary(int i, int j, int nx, int ny)
+{
+    return i == 0 || j == 0 || i == nx - 1 || j == ny - 1;
+}
+
+__device__ __forceinline__ void inward(int i, int j, int nx, int ny, int& ni, int& nj)
+{
+    ni = i == 0 ? 1 : (i == nx - 1 ? nx - 2 : i);
+    nj = j == 0 ? 1 : (j == ny - 1 ? ny - 2 : j);
+}
+
+// Non-equilibrium extrapolation onto a wall node from the nine values x_nb of
+// its inward neighbour: x_b = f_eq(P_nb, u_wall) + (x_nb - f_eq(P_nb, u_nb)).
+template <typename T>
+__device__ __forceinline__ void extrapolate(const T xnb[9], T uwall, T xb[9])
+{
+    T P, ux, uy, e_nb[9], e_w[9];
+    moments(xnb, P, ux, uy);
+    equilibrium(P, ux, uy, e_nb);
+    equilibrium(P, uwall, T(0), e_w);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) xb[k] = e_w[k] + (xnb[k] - e_nb[k]);
+}
+
+}  // namespace ifd

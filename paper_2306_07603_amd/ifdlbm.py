@@ -1,0 +1,257 @@
+"""Python binding of libifdlbm.so: the C ABI of include/ifdlbm.h, call by call.
+
+Only argument marshalling happens here (numpy host arrays and torch device
+tensors in, ctypes pointers out); every step of the method runs in the HIP
+kernels of the library.  Loading fails loudly when the library is missing:
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+try:   # load torch's HIP runtime first so that torch and the library share one
+    import torch  # noqa: F401
+except ImportError:
+    torch = None
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libifdlbm.so")
+
+IFDLBM_OK = 0
+IFDLBM_EINVAL = -1
+IFDLBM_ENOMEM = -2
+IFDLBM_EDEVICE = -3
+IFDLBM_EDIVERGED = -4
+IFDLBM_ENOTCONVERGED = -5
+
+IFDLBM_FP64, IFDLBM_FP32, IFDLBM_FP16DEV = 0, 1, 2
+IFDLBM_KERNEL_FUSED, IFDLBM_KERNEL_STAGED = 0, 1
+IFDLBM_STATUS_RUNNING, IFDLBM_STATUS_CONVERGED, IFDLBM_STATUS_DIVERGED, IFDLBM_STATUS_NOT_CONVERGED = 0, 1, 2, 3
+
+PRECISIONS = {"fp64": IFDLBM_FP64, "fp32": IFDLBM_FP32, "fp16dev": IFDLBM_FP16DEV}
+KERNELS = {"fused": IFDLBM_KERNEL_FUSED, "staged": IFDLBM_KERNEL_STAGED}
+
+
+class IfdlbmError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__("%s (code %d): %s" % (_strerror(code), code, message))
+        self.code = code
+
+
+class ifdlbm_cavity(ctypes.Structure):
+    _fields_ = [("n_xi", ctypes.c_int32), ("n_eta", ctypes.c_int32), ("re", ctypes.c_double),
+                ("n", ctypes.c_double), ("theta_deg", ctypes.c_double), ("u_lid", ctypes.c_double)]
+
+
+class ifdlbm_options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("cfl", ctypes.c_double), ("mix", ctypes.c_double),
+                ("rho0", ctypes.c_double), ("gamma_min", ctypes.c_double), ("residual_every", ctypes.c_int32),
+                ("kernel", ctypes.c_int32), ("batched", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
+                ("hip_stream", ctypes.c_void_p)]
+
+
+class ifdlbm_info_t(ctypes.Structure):
+    _fields_ = [("n_cavities", ctypes.c_int32), ("n_active", ctypes.c_int32), ("nodes", ctypes.c_int64),
+                ("state_bytes", ctypes.c_int64), ("alg_bytes_per_node", ctypes.c_double),
+                ("launches_per_step", ctypes.c_int32), ("work_items", ctypes.c_int64)]
+
+
+_lib = None
+_D = ctypes.POINTER(ctypes.c_double)
+_H = ctypes.c_void_p
+
+
+def lib():
+    """The loaded libifdlbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libifdlbm.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        L.ifdlbm_default_options.argtypes = [ctypes.POINTER(ifdlbm_options)]
+        L.ifdlbm_create.argtypes = [ctypes.POINTER(ifdlbm_cavity), ctypes.c_int32, ctypes.POINTER(ifdlbm_options),
+                                    ctypes.POINTER(_H)]
+        L.ifdlbm_step.argtypes = [_H, ctypes.c_int64]
+        L.ifdlbm_sync.argtypes = [_H]
+        L.ifdlbm_run_to_steady.argtypes = [_H, ctypes.c_double, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), _D, _D]
+        L.ifdlbm_get_residuals.argtypes = [_H, _D, _D]
+        L.ifdlbm_get_fields.argtypes = [_H, ctypes.c_int32, _D, _D, _D]
+        L.ifdlbm_get_fields_device.argtypes = [_H, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.c_int32]
+        L.ifdlbm_kinetic_energy.argtypes = [_H, ctypes.c_int32, _D]
+        L.ifdlbm_get_state.argtypes = [_H, ctypes.c_int32, _D, _D]
+        L.ifdlbm_set_state.argtypes = [_H, ctypes.c_int32, _D, _D]
+        L.ifdlbm_status.argtypes = [_H, ctypes.c_int32]
+        L.ifdlbm_info.argtypes = [_H, ctypes.POINTER(ifdlbm_info_t)]
+        L.ifdlbm_destroy.argtypes = [_H]
+        L.ifdlbm_destroy.restype = None
+        L.ifdlbm_strerror.argtypes = [ctypes.c_int]
+        L.ifdlbm_strerror.restype = ctypes.c_char_p
+        L.ifdlbm_last_error.argtypes = []
+        L.ifdlbm_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _strerror(code: int) -> str:
+    return lib().ifdlbm_strerror(code).decode()
+
+
+def _check(rc: int, allow=()) -> int:
+    if rc < 0 and rc not in allow:
+        raise IfdlbmError(rc, lib().ifdlbm_last_error().decode())
+    return rc
+
+
+def _dptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_D)
+
+
+@dataclass
+class Cavity:
+    """One cavity: grid size, Re of Eq. (2.15.1), n of Eq. (1.4), top angle, lid speed."""
+    n_xi: int
+    n_eta: int
+    re: float
+    n: float
+    theta_deg: float
+    u_lid: float = 0.1
+
+    def c(self) -> ifdlbm_cavity:
+        return ifdlbm_cavity(self.n_xi, self.n_eta, self.re, self.n, self.theta_deg, self.u_lid)
+
+
+def ifdlbm_default_options(**overrides) -> ifdlbm_options:
+    o = ifdlbm_options()
+    _check(lib().ifdlbm_default_options(ctypes.byref(o)))
+    for k, v in overrides.items():
+        if k == "precision" and isinstance(v, str):
+            v = PRECISIONS[v]
+        if k == "kernel" and isinstance(v, str):
+            v = KERNELS[v]
+        setattr(o, k, v)
+    return o
+
+
+class Handle:
+    """Owner of an ifdlbm_t*; the cavities it was created with are kept for array shapes."""
+
+    def __init__(self, ptr: int, cavities: Sequence[Cavity], options: ifdlbm_options):
+        self.ptr = ctypes.c_void_p(ptr)
+        self.cavities = list(cavities)
+        self.options = options
+
+    def shape(self, cav: int):
+        c = self.cavities[cav]
+        return (c.n_eta, c.n_xi)
+
+    def close(self):
+        if self.ptr:
+            lib().ifdlbm_destroy(self.ptr)
+            self.ptr = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ifdlbm_create(cavities: Sequence[Cavity], options: Optional[ifdlbm_options] = None) -> Handle:
+    options = options or ifdlbm_default_options()
+    arr = (ifdlbm_cavity * len(cavities))(*[c.c() for c in cavities])
+    out = _H()
+    _check(lib().ifdlbm_create(arr, len(cavities), ctypes.byref(options), ctypes.byref(out)))
+    return Handle(out.value, cavities, options)
+
+
+def ifdlbm_step(h: Handle, n_steps: int) -> None:
+    _check(lib().ifdlbm_step(h.ptr, int(n_steps)))
+
+
+def ifdlbm_sync(h: Handle) -> None:
+    _check(lib().ifdlbm_sync(h.ptr))
+
+
+def ifdlbm_run_to_steady(h: Handle, tol: float, max_steps: int):
+    """Returns (code, steps_done, res_u, res_p); code is OK, ENOTCONVERGED or EDIVERGED."""
+    n = len(h.cavities)
+    steps = (ctypes.c_int64 * n)()
+    ru, rp = np.zeros(n), np.zeros(n)
+    rc = _check(lib().ifdlbm_run_to_steady(h.ptr, float(tol), int(max_steps), steps, _dptr(ru), _dptr(rp)),
+                allow=(IFDLBM_ENOTCONVERGED, IFDLBM_EDIVERGED))
+    return rc, np.array(steps[:], dtype=np.int64), ru, rp
+
+
+def ifdlbm_get_residuals(h: Handle):
+    n = len(h.cavities)
+    ru, rp = np.zeros(n), np.zeros(n)
+    _check(lib().ifdlbm_get_residuals(h.ptr, _dptr(ru), _dptr(rp)))
+    return ru, rp
+
+
+def ifdlbm_get_fields(h: Handle, cav: int):
+    shp = h.shape(cav)
+    u, v, p = np.zeros(shp), np.zeros(shp), np.zeros(shp)
+    _check(lib().ifdlbm_get_fields(h.ptr, cav, _dptr(u), _dptr(v), _dptr(p)))
+    return u, v, p
+
+
+def ifdlbm_get_fields_device(h: Handle, cav: int, u, v, p) -> None:
+    """u, v, p: contiguous torch tensors of n_eta * n_xi float64 or float32 on the device."""
+    dt = {8: 0, 4: 1}[u.element_size()]
+    for t in (u, v, p):
+        assert t.is_contiguous() and t.numel() == h.shape(cav)[0] * h.shape(cav)[1] and t.element_size() == u.element_size()
+    _check(lib().ifdlbm_get_fields_device(h.ptr, cav, ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(v.data_ptr()),
+                                          ctypes.c_void_p(p.data_ptr()), dt))
+
+
+def ifdlbm_kinetic_energy(h: Handle, cav: int) -> float:
+    e = ctypes.c_double()
+    _check(lib().ifdlbm_kinetic_energy(h.ptr, cav, ctypes.byref(e)))
+    return e.value
+
+
+def ifdlbm_get_state(h: Handle, cav: int):
+    ny, nx = h.shape(cav)
+    F, L = np.zeros((9, ny, nx)), np.zeros((ny, nx))
+    _check(lib().ifdlbm_get_state(h.ptr, cav, _dptr(F), _dptr(L)))
+    return F, L
+
+
+def ifdlbm_set_state(h: Handle, cav: int, F: np.ndarray, L: np.ndarray) -> None:
+    ny, nx = h.shape(cav)
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    L = np.ascontiguousarray(L, dtype=np.float64)
+    assert F.shape == (9, ny, nx) and L.shape == (ny, nx)
+    _check(lib().ifdlbm_set_state(h.ptr, cav, _dptr(F), _dptr(L)))
+
+
+def ifdlbm_status(h: Handle, cav: int) -> int:
+    return _check(lib().ifdlbm_status(h.ptr, cav))
+
+
+def ifdlbm_info(h: Handle) -> dict:
+    i = ifdlbm_info_t()
+    _check(lib().ifdlbm_info(h.ptr, ctypes.byref(i)))
+    return {k: getattr(i, k) for k, _ in ifdlbm_info_t._fields_}
+
+
+def ifdlbm_destroy(h: Handle) -> None:
+    h.close()
+
+
+def ifdlbm_strerror(code: int) -> str:
+    return _strerror(code)
+
+
+def ifdlbm_last_error() -> str:
+    return lib().ifdlbm_last_error().decode()
