@@ -55,10 +55,16 @@ typedef struct ifdlbm_s ifdlbm_t;
 #define IFDLBM_FP32     1   /* FP32 deviations f-hat - omega_k rho0, FP32 arithmetic             */
 #define IFDLBM_FP16DEV  2   /* FP16 scaled deviations (f-hat - omega_k rho0)/omega_k, FP32 lambda
                                and FP32 arithmetic                                                 */
+#define IFDLBM_FP32X    3   /* FP32 deviations and lambda in memory, FP64 arithmetic               */
 
 /* kernel schedule (options.kernel) */
 #define IFDLBM_KERNEL_FUSED    0   /* one fused launch per step (default)                        */
 #define IFDLBM_KERNEL_STAGED   1   /* five staged launches per step through HBM temporaries       */
+
+/* time-step rule (options.dt_rule) */
+#define IFDLBM_DT_CONTRAVARIANT 0  /* dt = cfl / max(|c_xi|/dxi, |c_eta|/deta), max |c_xi| = 1 + cot(theta):
+                                      the Courant number of the transformed Eqs. (3.6)-(3.7) (default)   */
+#define IFDLBM_DT_CARTESIAN     1  /* dt = cfl * min(dxi, deta) / c with c = 1                          */
 
 /* cavity status (ifdlbm_status) */
 #define IFDLBM_STATUS_RUNNING       0
@@ -77,8 +83,8 @@ typedef struct {
 } ifdlbm_cavity;
 
 typedef struct {
-    int32_t precision;      /* IFDLBM_FP64 | IFDLBM_FP32 | IFDLBM_FP16DEV                             */
-    double  cfl;            /* dt = cfl * min(dxi, deta) / c with c = 1, > 0 (paper: 0.5)             */
+    int32_t precision;      /* IFDLBM_FP64 | IFDLBM_FP32 | IFDLBM_FP16DEV | IFDLBM_FP32X              */
+    double  cfl;            /* Courant number, > 0 (paper: 0.5); dt follows dt_rule                   */
     double  mix;            /* weight of the central scheme in Eq. (2.5), [0, 1] (default 0.5)       */
     double  rho0;           /* constant density of Eq. (2.8) (default 1); u and P do not depend on it */
     double  gamma_min;      /* floor of the shear rate in Eq. (1.4), > 0 (default 1e-6)              */
@@ -86,6 +92,7 @@ typedef struct {
     int32_t kernel;         /* IFDLBM_KERNEL_FUSED | IFDLBM_KERNEL_STAGED                             */
     int32_t batched;        /* 1: all cavities in one launch per step; 0: one launch per cavity       */
     int32_t graph_steps;    /* > 0: replay steps from a captured HIP graph of this many steps         */
+    int32_t dt_rule;        /* IFDLBM_DT_CONTRAVARIANT | IFDLBM_DT_CARTESIAN                          */
     void*   hip_stream;     /* hipStream_t to enqueue on, or NULL for the null stream                 */
 } ifdlbm_options;
 
@@ -101,7 +108,7 @@ typedef struct {
 } ifdlbm_info_t;
 
 /* Fills *opt with the defaults: FP64, cfl 0.5, mix 0.5, rho0 1, gamma_min 1e-6, residual_every 1,
-   fused kernel, batched, no graph, null stream. */
+   fused kernel, batched, no graph, contravariant time-step rule, null stream. */
 int ifdlbm_default_options(ifdlbm_options* opt);
 
 /* Validates cav[0..n_cav) and *opt, builds the metric terms of Eqs. (3.2)-(3.8.2) in FP64 on the host,
@@ -152,6 +159,20 @@ int ifdlbm_status(ifdlbm_t* h, int32_t cav);
 
 /* Work sizes of the handle (see ifdlbm_info_t). */
 int ifdlbm_info(ifdlbm_t* h, ifdlbm_info_t* info);
+
+/* Objectives of ifdlbm_gradient */
+#define IFDLBM_OBJ_KINETIC_ENERGY 0   /* Eq. (5.1) after the last step */
+
+/* Objective J of one cavity after n_steps >= 1 steps from Step (1), and its derivatives grad[0] = dJ/dtheta
+   (theta in radians), grad[1] = dJ/dn, grad[2] = dJ/du_lid, by forward (tangent-linear) differentiation of the
+   discrete step: every quantity of the step carries its three partial derivatives in FP64.  The parameters
+   enter through the metric terms (Eqs. 3.2-3.8.2), the time step (dt_rule), K = U^(2-n)/Re (Eq. 2.15.1), the
+   exponent of Eq. (1.4), the lid condition (Eq. 1.5) and the initial lambda.  Options cfl, mix, gamma_min,
+   dt_rule and hip_stream apply; precision, kernel, batching, graphs and residual_every do not.  Device memory
+   (about 100 doubles per node) is allocated and freed inside the call, which synchronises the stream.
+   J and grad are caller-owned.  Errors: EINVAL, ENOMEM, EDEVICE. */
+int ifdlbm_gradient(const ifdlbm_cavity* cav, const ifdlbm_options* opt, int64_t n_steps, int32_t objective,
+                    double* J, double grad[3]);
 
 /* Frees the handle and its device memory; NULL-safe. */
 void ifdlbm_destroy(ifdlbm_t* h);

@@ -25,6 +25,7 @@ _SRC = os.path.join(_HERE, "ifdlbm_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 CAVITY, COUETTE, PERIODIC = 0, 1, 2
+DT_CONTRAVARIANT, DT_CARTESIAN = 0, 1
 
 
 def compile_source(src: str, out: str) -> str:
@@ -48,7 +49,7 @@ class _Params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("re", ctypes.c_double),
                 ("n", ctypes.c_double), ("theta_deg", ctypes.c_double), ("u_lid", ctypes.c_double),
                 ("cfl", ctypes.c_double), ("mix", ctypes.c_double), ("rho0", ctypes.c_double),
-                ("gamma_min", ctypes.c_double), ("bc_mode", ctypes.c_int)]
+                ("gamma_min", ctypes.c_double), ("bc_mode", ctypes.c_int), ("dt_rule", ctypes.c_int)]
 
 
 class _Derived(ctypes.Structure):
@@ -127,10 +128,11 @@ class Params:
     rho0: float = 1.0
     gamma_min: float = 1e-6
     bc_mode: int = CAVITY
+    dt_rule: int = DT_CONTRAVARIANT
 
     def c(self) -> _Params:
         return _Params(self.nx, self.ny, self.re, self.n, self.theta_deg, self.u_lid, self.cfl,
-                       self.mix, self.rho0, self.gamma_min, self.bc_mode)
+                       self.mix, self.rho0, self.gamma_min, self.bc_mode, self.dt_rule)
 
 
 def derive(p: Params) -> dict:

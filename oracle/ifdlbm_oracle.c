@@ -34,8 +34,16 @@
  *      gamma^2 = 2 D:D.  Initial lambda_0 = U L / (Re c_s^2).
  *  R10 Eq. (2.15.1): K = U^(2-n) L^n / Re with L = 1 (cavity height) and
  *      U = |u_lid|.
- *  R11 dt = cfl * min(dxi, deta) / c, dxi = 1/(nx-1), deta = 1/(ny-1).
- *      Periodic directions hold N distinct nodes and use spacing 1/N.
+ *  R11 CFL = 0.5 of Section 5 is the Courant number of the transformed
+ *      equations (3.6)-(3.7): dt = cfl / max(|c_k,xi|/dxi, |c_k,eta|/deta),
+ *      where max |c_k,xi| = 1 + cot(theta) (diagonal populations at the
+ *      bottom corners, Eqs. 3.2, 3.8.2) and |c_k,eta| <= 1; on the square
+ *      this is the paper's dt = cfl * dx / c.  (The literal Cartesian rule
+ *      dt = cfl * min(dxi, deta) / c is kept as an option; on trapezoids it
+ *      puts the corner Courant number at 1 + cot(theta)/2 and is unstable
+ *      where the fluid is nearly collisionless.)  dxi = 1/(nx-1),
+ *      deta = 1/(ny-1); periodic directions hold N distinct nodes and use
+ *      spacing 1/N.
  *  R12 Step (2) uses the lambda stored with f-hat (the previous step's, as
  *      Section 3 prescribes) both to recover f by Eq. (2.18) and in
  *      Eq. (2.12); the new lambda is used by Steps (3)-(5).
@@ -123,14 +131,20 @@ int orc_derive(const orc_params* p, orc_derived* d)
     if (!(p->mix >= 0.0 && p->mix <= 1.0) || !(p->gamma_min > 0.0)) return -1;
     if (p->bc_mode != ORC_CAVITY && p->theta_deg != 90.0) return -1;
     if (p->bc_mode < ORC_CAVITY || p->bc_mode > ORC_PERIODIC) return -1;
+    if (p->dt_rule != ORC_DT_CONTRAVARIANT && p->dt_rule != ORC_DT_CARTESIAN) return -1;
     /* R11 */
     d->dxi = (p->bc_mode == ORC_CAVITY) ? 1.0 / (p->nx - 1) : 1.0 / p->nx;
     d->deta = (p->bc_mode == ORC_PERIODIC) ? 1.0 / p->ny : 1.0 / (p->ny - 1);
-    d->dt = p->cfl * (d->dxi < d->deta ? d->dxi : d->deta) / 1.0;
+    d->cot = cot_deg(p->theta_deg);
+    if (p->dt_rule == ORC_DT_CARTESIAN) {
+        d->dt = p->cfl * (d->dxi < d->deta ? d->dxi : d->deta) / 1.0;
+    } else {
+        double sxi = (1.0 + d->cot) / d->dxi, seta = 1.0 / d->deta;
+        d->dt = p->cfl / (sxi > seta ? sxi : seta);
+    }
     /* R10: Re = U^(2-n) L^n / K with L = 1 */
     double U = fabs(p->u_lid);
     d->K = pow(U, 2.0 - p->n) / p->re;
-    d->cot = cot_deg(p->theta_deg);
     /* R9: lambda_0 = U L / (Re c_s^2) */
     d->lam0 = U / (p->re * CS2);
     return 0;

@@ -43,7 +43,15 @@ typedef struct {
     double rho0;        /* constant density rho_0 of Eq. (2.8)               */
     double gamma_min;   /* floor of the shear rate in Eq. (1.4)              */
     int    bc_mode;     /* ORC_CAVITY, ORC_COUETTE or ORC_PERIODIC           */
+    int    dt_rule;     /* ORC_DT_CONTRAVARIANT or ORC_DT_CARTESIAN          */
 } orc_params;
+
+/* dt_rule values (reading R11).  CONTRAVARIANT: dt = cfl / max(|c_xi|/dxi,
+ * |c_eta|/deta) over the grid, the Courant number of the transformed
+ * equations (3.6)-(3.7); max |c_xi| = 1 + cot(theta) at the bottom corners.
+ * CARTESIAN: dt = cfl * min(dxi, deta) / c.  Both equal cfl * dxi on the
+ * square. */
+enum { ORC_DT_CONTRAVARIANT = 0, ORC_DT_CARTESIAN = 1 };
 
 /* Derived constants of one run. */
 typedef struct {

@@ -39,9 +39,9 @@ constexpr int kSegRows = 64;
 
 int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
-size_t f_elem_size(int prec) { return prec == P_FP64 ? 8 : (prec == P_FP32 ? 4 : 2); }
+size_t f_elem_size(int prec) { return prec == P_FP64 ? 8 : (prec == P_FP16DEV ? 2 : 4); }
 size_t l_elem_size(int prec) { return prec == P_FP64 ? 8 : 4; }
-size_t t_elem_size(int prec) { return prec == P_FP64 ? 8 : 4; }
+size_t t_elem_size(int prec) { return (prec == P_FP64 || prec == P_FP32X) ? 8 : 4; }
 
 // 1/tan(theta) with theta in degrees; exactly 0 for the square.
 double cot_deg(double theta_deg)
@@ -327,9 +327,10 @@ int ifdlbm_default_options(ifdlbm_options* opt)
     opt->rho0 = 1.0;
     opt->gamma_min = 1e-6;
     opt->residual_every = 1;
-    opt->kernel = IFDLBM_KERNEL_STAGED;
+    opt->kernel = IFDLBM_KERNEL_FUSED;
     opt->batched = 1;
     opt->graph_steps = 0;
+    opt->dt_rule = IFDLBM_DT_CONTRAVARIANT;
     opt->hip_stream = nullptr;
     return IFDLBM_OK;
 }
@@ -340,11 +341,12 @@ int ifdlbm_create(const ifdlbm_cavity* cav, int32_t n_cav, const ifdlbm_options*
     *out = nullptr;
     if (!cav || !opt || n_cav <= 0) return fail(IFDLBM_EINVAL, "need at least one cavity and options");
     const ifdlbm_options& o = *opt;
-    if (o.precision < IFDLBM_FP64 || o.precision > IFDLBM_FP16DEV) return fail(IFDLBM_EINVAL, "unknown precision");
+    if (o.precision < IFDLBM_FP64 || o.precision > IFDLBM_FP32X) return fail(IFDLBM_EINVAL, "unknown precision");
     if (!(o.cfl > 0.0) || !(o.mix >= 0.0 && o.mix <= 1.0) || !(o.gamma_min > 0.0) || !std::isfinite(o.rho0))
         return fail(IFDLBM_EINVAL, "cfl must be > 0, mix in [0, 1], gamma_min > 0, rho0 finite");
     if (o.residual_every < 1) return fail(IFDLBM_EINVAL, "residual_every must be >= 1");
     if (o.kernel != IFDLBM_KERNEL_FUSED && o.kernel != IFDLBM_KERNEL_STAGED) return fail(IFDLBM_EINVAL, "unknown kernel");
+    if (o.dt_rule != IFDLBM_DT_CONTRAVARIANT && o.dt_rule != IFDLBM_DT_CARTESIAN) return fail(IFDLBM_EINVAL, "unknown dt_rule");
     if (o.graph_steps < 0 || (o.graph_steps > 0 && (o.graph_steps % 2 != 0 || o.graph_steps % o.residual_every != 0)))
         return fail(IFDLBM_EINVAL, "graph_steps must be 0, or even and a multiple of residual_every");
     for (int c = 0; c < n_cav; ++c) {
@@ -409,7 +411,10 @@ int ifdlbm_create(const ifdlbm_cavity* cav, int32_t n_cav, const ifdlbm_options*
         for (int j = 0; j < d.ny; ++j) geo.push_back(1.0 / (1.0 + 2.0 * d.cot * (j * d.deta)));   // a_j = 1/J
         for (int i = 0; i < d.nx; ++i) geo.push_back(d.cot * (double)(2 * i - (d.nx - 1)) / (double)(d.nx - 1));   // s_i = x_eta
         const double U = std::fabs(v.u_lid);
-        d.dt = o.cfl * std::min(d.dxi, d.deta);
+        if (o.dt_rule == IFDLBM_DT_CARTESIAN)
+            d.dt = o.cfl * std::min(d.dxi, d.deta);
+        else   // largest contravariant speed: |c_xi| <= 1 + cot(theta) at the bottom corners, |c_eta| <= 1
+            d.dt = o.cfl / std::max((1.0 + d.cot) / d.dxi, 1.0 / d.deta);
         d.K = std::pow(U, 2.0 - v.n) / v.re;   // Eq. (2.15.1), L = 1
         d.expo = 0.5 * (v.n - 1.0);
         d.g2min = o.gamma_min * o.gamma_min;
@@ -684,6 +689,36 @@ int ifdlbm_info(ifdlbm_t* h, ifdlbm_info_t* info)
     if (!h->opt.batched) launches *= info->n_active;
     info->launches_per_step = launches;
     info->work_items = h->opt.kernel == IFDLBM_KERNEL_STAGED ? (int64_t)h->act_blocks.size() : (int64_t)h->act_items.size();
+    return IFDLBM_OK;
+}
+
+int ifdlbm_gradient(const ifdlbm_cavity* cav, const ifdlbm_options* opt, int64_t n_steps, int32_t objective, double* J,
+                    double grad[3])
+{
+    if (!cav || !opt || !J || !grad) return fail(IFDLBM_EINVAL, "null argument");
+    if (objective != IFDLBM_OBJ_KINETIC_ENERGY) return fail(IFDLBM_EINVAL, "unknown objective");
+    if (n_steps < 1) return fail(IFDLBM_EINVAL, "n_steps must be >= 1");
+    const ifdlbm_cavity& v = *cav;
+    if (v.n_xi < 5 || v.n_eta < 5 || (int64_t)v.n_xi * v.n_eta > (int64_t)1 << 26)
+        return fail(IFDLBM_EINVAL, "n_xi, n_eta must be >= 5 and n_xi * n_eta <= 2^26");
+    if (!(v.theta_deg > 0.0 && v.theta_deg <= 90.0) || !(v.n > 0.0) || !(v.re > 0.0) || !(v.u_lid != 0.0) ||
+        !std::isfinite(v.n) || !std::isfinite(v.re) || !std::isfinite(v.u_lid))
+        return fail(IFDLBM_EINVAL, "cavity parameters outside their domain");
+    if (!(opt->cfl > 0.0) || !(opt->mix >= 0.0 && opt->mix <= 1.0) || !(opt->gamma_min > 0.0) ||
+        (opt->dt_rule != IFDLBM_DT_CONTRAVARIANT && opt->dt_rule != IFDLBM_DT_CARTESIAN))
+        return fail(IFDLBM_EINVAL, "options outside their domain");
+    hipStream_t s = static_cast<hipStream_t>(opt->hip_stream);
+    bool own = false;
+    if (!s) {
+        IFD_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        own = true;
+    }
+    std::string err;
+    hipError_t e = tangent_kinetic_energy(v.n_xi, v.n_eta, v.re, v.n, v.theta_deg, v.u_lid, opt->cfl, opt->mix,
+                                          opt->gamma_min, opt->dt_rule, n_steps, s, J, grad, err);
+    if (own) (void)hipStreamDestroy(s);
+    if (e != hipSuccess)
+        return fail(e == hipErrorOutOfMemory ? IFDLBM_ENOMEM : IFDLBM_EDEVICE, err);
     return IFDLBM_OK;
 }
 

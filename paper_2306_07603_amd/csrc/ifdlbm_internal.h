@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "lbm_device.h"
 
 namespace ifd {
@@ -84,5 +86,10 @@ hipError_t launch_state_in(int prec, void* f, void* l, const CavityDesc& hd, dou
 // Kinetic energy of Eq. (5.1) summed per block, reduced on the host in order.
 hipError_t launch_energy(int prec, const void* f, const CavityDesc* desc, const double* geo, int cav_index,
                          const CavityDesc& hd, double* partial, hipStream_t s);
+
+// Tangent-linear kinetic energy of one cavity after n_steps (see ifdlbm_gradient).
+hipError_t tangent_kinetic_energy(int nx, int ny, double re, double n, double theta_deg, double u_lid, double cfl,
+                                  double mix, double gamma_min, int dt_rule, int64_t n_steps, hipStream_t s, double* J,
+                                  double* grad, std::string& err);
 
 }  // namespace ifd

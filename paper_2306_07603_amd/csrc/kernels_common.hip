@@ -145,6 +145,7 @@ hipError_t launch_init(int prec, void* f, void* l, const CavityDesc* desc, const
     case P_FP64: hipLaunchKernelGGL(k_init<P_FP64>, dim3(nb), dim3(kNodeBlock), 0, s, f, l, desc, blocks); break;
     case P_FP32: hipLaunchKernelGGL(k_init<P_FP32>, dim3(nb), dim3(kNodeBlock), 0, s, f, l, desc, blocks); break;
     case P_FP16DEV: hipLaunchKernelGGL(k_init<P_FP16DEV>, dim3(nb), dim3(kNodeBlock), 0, s, f, l, desc, blocks); break;
+    case P_FP32X: hipLaunchKernelGGL(k_init<P_FP32X>, dim3(nb), dim3(kNodeBlock), 0, s, f, l, desc, blocks); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -171,6 +172,7 @@ hipError_t launch_fields(int prec, const void* f, const CavityDesc*, int, const 
     case P_FP64: IFD_FIELDS(P_FP64) break;
     case P_FP32: IFD_FIELDS(P_FP32) break;
     case P_FP16DEV: IFD_FIELDS(P_FP16DEV) break;
+    case P_FP32X: IFD_FIELDS(P_FP32X) break;
     default: return hipErrorInvalidValue;
     }
 #undef IFD_FIELDS
@@ -185,6 +187,7 @@ hipError_t launch_state_out(int prec, const void* f, const void* l, const Cavity
     case P_FP64: hipLaunchKernelGGL(k_state_out<P_FP64>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
     case P_FP32: hipLaunchKernelGGL(k_state_out<P_FP32>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
     case P_FP16DEV: hipLaunchKernelGGL(k_state_out<P_FP16DEV>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
+    case P_FP32X: hipLaunchKernelGGL(k_state_out<P_FP32X>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -198,6 +201,7 @@ hipError_t launch_state_in(int prec, void* f, void* l, const CavityDesc& hd, dou
     case P_FP64: hipLaunchKernelGGL(k_state_in<P_FP64>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
     case P_FP32: hipLaunchKernelGGL(k_state_in<P_FP32>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
     case P_FP16DEV: hipLaunchKernelGGL(k_state_in<P_FP16DEV>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
+    case P_FP32X: hipLaunchKernelGGL(k_state_in<P_FP32X>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -211,6 +215,7 @@ hipError_t launch_energy(int prec, const void* f, const CavityDesc*, const doubl
     case P_FP64: hipLaunchKernelGGL(k_energy<P_FP64>, g, b, 0, s, f, hd, partial); break;
     case P_FP32: hipLaunchKernelGGL(k_energy<P_FP32>, g, b, 0, s, f, hd, partial); break;
     case P_FP16DEV: hipLaunchKernelGGL(k_energy<P_FP16DEV>, g, b, 0, s, f, hd, partial); break;
+    case P_FP32X: hipLaunchKernelGGL(k_energy<P_FP32X>, g, b, 0, s, f, hd, partial); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -15,7 +15,7 @@
 
 namespace ifd {
 
-enum Precision { P_FP64 = 0, P_FP32 = 1, P_FP16DEV = 2 };
+enum Precision { P_FP64 = 0, P_FP32 = 1, P_FP16DEV = 2, P_FP32X = 3 };
 
 // One cavity in the device tables.  Planes are SoA: population k of node
 // (i, j) lives at f_off + k * plane + j * pitch + i.
@@ -59,6 +59,15 @@ template <> struct Storage<P_FP32> {
     using T = float;
     __device__ static inline T load(const F* p, int64_t i, int) { return p[i]; }
     __device__ static inline void store(F* p, int64_t i, int, T v) { p[i] = v; }
+};
+
+// FP32 storage with FP64 arithmetic: only the stored state is rounded to FP32.
+template <> struct Storage<P_FP32X> {
+    using F = float;
+    using L = float;
+    using T = double;
+    __device__ static inline T load(const F* p, int64_t i, int) { return (T)p[i]; }
+    __device__ static inline void store(F* p, int64_t i, int, T v) { p[i] = (F)v; }
 };
 
 // FP16 storage of g_k / omega_k: the division by the lattice weight puts all
@@ -111,6 +120,18 @@ __device__ __forceinline__ void equilibrium(T P, T ux, T uy, T e[9])
     e[8] = w5 * q(ux - uy);
 }
 
+// 1/x for x > 0: v_rcp_f32 (1 ulp) in FP32; v_rcp_f64 refined by two Newton
+// steps r <- r (2 - x r) in FP64 (relative error squares at each step).
+template <typename T> __device__ __forceinline__ T recip(T x);
+template <> __device__ __forceinline__ float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double recip<double>(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = r * __builtin_fma(-x, r, 2.0);
+    r = r * __builtin_fma(-x, r, 2.0);
+    return r;
+}
+
 template <typename T> __device__ __forceinline__ T pow_pos(T x, T y);
 template <> __device__ __forceinline__ double pow_pos<double>(double x, double y) { return pow(x, y); }
 template <> __device__ __forceinline__ float pow_pos<float>(float x, float y)
@@ -135,7 +156,7 @@ __device__ __forceinline__ T relaxation_time(const T g[9], const T e[9], T lam_o
     const T pxx = (n[1] + n[3]) + s58;
     const T pyy = (n[2] + n[4]) + s58;
     const T pxy = (n[5] - n[6]) + (n[7] - n[8]);
-    const T r = T(1) / (T(2) * lam_old + T(c.dt));
+    const T r = recip(T(2) * lam_old + T(c.dt));
     T gamma2 = T(18) * (pxx * pxx + T(2) * pxy * pxy + pyy * pyy) * r * r;
     gamma2 = gamma2 > T(c.g2min) ? gamma2 : T(c.g2min);
     return T(3) * T(c.K) * pow_pos<T>(gamma2, T(c.expo));
@@ -148,7 +169,7 @@ struct Collision {
     T a_hat, b_hat, a_bar, b_bar;
     __device__ __forceinline__ Collision(T lam, T dt)
     {
-        const T r = T(1) / (T(2) * lam + dt);
+        const T r = recip(T(2) * lam + dt);
         a_hat = (T(2) * lam - dt) * r;
         b_hat = T(2) * dt * r;
         a_bar = (T(4) * lam - dt) * (T(0.5) * r);
@@ -162,7 +183,7 @@ struct HalfStep {
     T a, b;
     __device__ __forceinline__ HalfStep(T lam, T dt)
     {
-        const T r = T(1) / (T(4) * lam + dt);
+        const T r = recip(T(4) * lam + dt);
         a = T(4) * lam * r;
         b = dt * r;
     }

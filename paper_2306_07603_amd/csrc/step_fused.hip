@@ -1,71 +1,92 @@
 // step_fused.hip -- one launch per IFDLBM time step (arXiv:2306.07603,
 // Section 4, Steps (2)-(6)); each wavefront reads the state of its work item
-// once and writes it once.
+// once from HBM and writes it once.
 //
 // Work item: output columns [i0, i1) and rows [j0, j1) of one cavity.  The 64
 // lanes of the wavefront hold columns i0 - 4 .. i0 + 59, one column per lane,
 // and march up the rows.  At row t of the march:
-//   A  (row t)     load f-hat and lambda, moments, lambda (Step 2), f-hat+
-//                  and f-bar+ (Eqs. 2.15-2.16)
+//   A  (row t)     f-hat and lambda (prefetched one row ahead): moments,
+//                  lambda (Step 2), f-bar+ (Eq. 2.16)
 //   B  (row t - 2) f-bar(t + dt/2) by Eq. (3.7), walls by extrapolation, and
 //                  f(t + dt/2) by Eq. (2.17)
-//   C  (row t - 4) f-hat(t + dt) by Eq. (3.6), walls by extrapolation (Step 6),
-//                  store, residual partial sums of Eq. (2.19)
-// The eta-direction stencils read five-row register rings; the xi-direction
-// stencils read neighbour lanes through a 64-entry LDS row per population.
-// The halo costs 8 of 64 lanes across xi and 8 + 4 recomputed rows per
-// segment along eta.  The bottom wall row is produced together with row 1 (its
-// extrapolation source), the top wall row from the row below it.
+//   C  (row t - 4) f-hat+ (Eq. 2.15) recomputed from f-hat of row t - 4
+//                  (read again; it is still in L2), f-hat(t + dt) by
+//                  Eq. (3.6), walls by extrapolation (Step 6), store, residual
+//                  partial sums of Eq. (2.19)
+// The eta-direction stencils read five-row register rings of f-bar+ and
+// f(t + dt/2); the xi-direction stencils read neighbour lanes through one LDS
+// row per population.  The halo costs 8 of 64 lanes across xi and 8 + 4
+// recomputed rows per segment along eta.  The bottom wall row is produced with
+// row 1 (its extrapolation source), the lid row from the row below it.
 #include "ifdlbm_internal.h"
 
 namespace ifd {
 namespace {
 
 constexpr int kPad = 2;
+constexpr int kXcds = 8;   // MI355X: workgroups are dealt to the 8 XCDs in turn
 
 template <typename T> __device__ __forceinline__ const T* geo_of(const StepArgs& a);
 template <> __device__ __forceinline__ const double* geo_of<double>(const StepArgs& a) { return a.geo; }
 template <> __device__ __forceinline__ const float* geo_of<float>(const StepArgs& a) { return a.geo32; }
 
-// Second-order upwind or first-order one-sided part and central part of
-// Eq. (2.5) along xi for one population, from the LDS row of the wavefront;
-// returns eps * central + (1 - eps) * upwind, times 2 dxi.
-template <typename T>
-__device__ __forceinline__ T xi_diff(const T* row, int lane, T c0, bool pos, bool lo, bool hi, T eps)
+// Work item of block b among nw: consecutive items (neighbouring strips and
+// segments, which share halo rows and columns) go to the same XCD and L2.
+__device__ __forceinline__ int xcd_order(int b, int nw)
 {
-    const T m2 = row[lane + kPad - 2], m1 = row[lane + kPad - 1];
-    const T p1 = row[lane + kPad + 1], p2 = row[lane + kPad + 2];
-    return mixed_diff_2h(m2, m1, c0, p1, p2, pos, lo, hi, eps);
+    const int q = nw / kXcds, r = nw % kXcds, x = b % kXcds;
+    return x * q + min(x, r) + b / kXcds;
 }
 
-// The same along eta for population k, from the ring slots of rows q-2..q+2;
-// the sign of c_k,eta = c_ky is fixed by k.
-template <typename T, int K>
-__device__ __forceinline__ T eta_diff(const T (&ring)[5][9], bool lo, bool hi, T eps)
+// Eq. (2.5) times sign(c) * 2h from the upwind-side points a1 (one behind)
+// and a2 (two behind) and the point f1 one ahead: sign(c) * central = f1 - a1,
+// sign(c) * upwind = 3 c0 - 4 a1 + a2 (Eqs. 2.6-2.7).  Multiplied by |c| it is
+// c * (eps * central + (1 - eps) * upwind).
+template <typename T>
+__device__ __forceinline__ T mixed_signed(T a2, T a1, T c0, T f1, T eps, T ome)
 {
-    return mixed_diff_2h(ring[0][K], ring[1][K], ring[2][K], ring[3][K], ring[4][K], cyk(K) > 0, lo, hi, eps);
+    return eps * (f1 - a1) + ome * ((T(3) * c0 - T(4) * a1) + a2);
 }
 
-// c_k . grad Phi_k (Eq. 3.4) times 2 dxi resp. 2 deta folded into the scales:
-// out[k] = base[k] - step * (sx * dk[k] * D_xi + cy_k * sy * D_eta).
-template <typename T>
+// c_k . grad Phi_k of Eq. (3.4) for the eight moving populations of one row,
+// times `step`, subtracted from `base`:
+//   out[k] = base[k] - step * (sx * |dk[k]| * D_xi + sy * D_eta)
+// with D the signed mixed differences; the xi neighbours come from the LDS
+// row, the eta neighbours from ring slots 0..4 (rows r-2..r+2).  Where the
+// second upwind point would leave the grid (EDGE waves) it is replaced by the
+// linear extrapolation 2 a1 - c0, which gives the first-order difference.
+template <typename T, bool EDGE>
 __device__ __forceinline__ void transport_row(T (*xs)[kWaveLanes + 2 * kPad], int lane, const T (&ring)[5][9],
-                                              const T (&base)[9], const T (&dk)[9], const bool (&pos)[9], bool lo, bool hi,
-                                              bool lo_eta, bool hi_eta, T sx, T sy, T step, T eps, T (&out)[9])
+                                              const T (&base)[9], const T (&adk)[9], const bool (&pos)[9],
+                                              const bool (&edge)[9], bool lo_eta, bool hi_eta, T sx, T sy, T step,
+                                              T eps, T ome, T (&out)[9])
 {
 #pragma unroll
     for (int k = 1; k < 9; ++k) xs[k - 1][lane + kPad] = ring[2][k];
     __syncthreads();
     out[0] = base[0];
-#define IFD_K(K)                                                                                   \
-    {                                                                                              \
-        const T dx = xi_diff(xs[K - 1], lane, ring[2][K], pos[K], lo, hi, eps);                    \
-        T term = sx * dk[K] * dx;                                                                  \
-        if (cyk(K) != 0) term += T(cyk(K)) * sy * eta_diff<T, K>(ring, lo_eta, hi_eta, eps);       \
-        out[K] = base[K] - step * term;                                                            \
+#pragma unroll
+    for (int k = 1; k < 9; ++k) {
+        const T* row = xs[k - 1];
+        const T c0 = ring[2][k];
+        const T m2 = row[lane + kPad - 2], m1 = row[lane + kPad - 1];
+        const T p1 = row[lane + kPad + 1], p2 = row[lane + kPad + 2];
+        const T a1 = pos[k] ? m1 : p1;
+        T a2 = pos[k] ? m2 : p2;
+        const T f1 = pos[k] ? p1 : m1;
+        if (EDGE) a2 = edge[k] ? T(2) * a1 - c0 : a2;
+        T term = sx * adk[k] * mixed_signed(a2, a1, c0, f1, eps, ome);
+        if (cyk(k) != 0) {
+            // sign of c_k,eta = c_ky is fixed by k
+            const bool up = cyk(k) > 0;
+            const T e1 = up ? ring[1][k] : ring[3][k];
+            T e2 = up ? ring[0][k] : ring[4][k];
+            const T g1 = up ? ring[3][k] : ring[1][k];
+            if ((up && lo_eta) || (!up && hi_eta)) e2 = T(2) * e1 - c0;
+            term += sy * mixed_signed(e2, e1, c0, g1, eps, ome);
+        }
+        out[k] = base[k] - step * term;
     }
-    IFD_K(1) IFD_K(2) IFD_K(3) IFD_K(4) IFD_K(5) IFD_K(6) IFD_K(7) IFD_K(8)
-#undef IFD_K
     __syncthreads();
 }
 
@@ -80,9 +101,9 @@ __device__ __forceinline__ void publish(T (*w)[9], int i, int nx, const T (&x)[9
         for (int k = 0; k < 9; ++k) w[1][k] = x[k];
 }
 
-// Extrapolation source of a wall node at the same level: its own inward
-// neighbour's values (same lane, `own`) for interior columns, the published
-// values of column 1 or nx - 2 for the two side columns.
+// Extrapolation source of a wall node: its inward neighbour at the same level,
+// which is the lane's own `own` for interior columns and the published values
+// of column 1 or nx - 2 for the two side columns.
 template <typename T>
 __device__ __forceinline__ void wall_source(T (*w)[9], int i, int nx, const T (&own)[9], T (&src)[9])
 {
@@ -118,85 +139,110 @@ __device__ __forceinline__ void residual_add(const T (&gn)[9], const T (&old)[3]
     acc[6] += (isfinite((double)ux) && isfinite((double)uy) && isfinite((double)P)) ? 0.0 : 1.0;
 }
 
-template <int PREC, bool RES>
-__global__ __launch_bounds__(kWaveLanes) void k_fused(StepArgs a, const StripItem* items, int w0)
+// LDS of one wavefront.
+template <typename T>
+struct WaveLds {
+    T xs[8][kWaveLanes + 2 * kPad];   // one row of each moving population, for the xi stencils
+    T wb[2][9];                       // f-bar of columns 1 and nx-2 at the current half-step row
+    T wc[2][9];                       // f-hat(t+dt) of columns 1 and nx-2 at the current full-step row
+    T keep_b[9][kWaveLanes];          // f-bar of row ny-2, source of the lid row
+    T keep_c[9][kWaveLanes];          // f-hat(t+dt) of row ny-2, source of the lid row
+};
+
+template <int PREC, bool RES, bool EDGE>
+__device__ __forceinline__ void fused_item(const StepArgs& a, const StripItem& it, const CavityDesc& c,
+                                           WaveLds<typename Storage<PREC>::T>& sh, double (&acc)[kPartials])
 {
     using S = Storage<PREC>;
     using T = typename S::T;
-    __shared__ T xs[8][kWaveLanes + 2 * kPad];
-    __shared__ T wb[2][9];   // f-bar of columns 1 and nx-2 at the current half-step row
-    __shared__ T wc[2][9];   // f-hat(t+dt) of columns 1 and nx-2 at the current full-step row
+    auto& xs = sh.xs;
+    auto& wb = sh.wb;
+    auto& wc = sh.wc;
+    auto& keep_b = sh.keep_b;
+    auto& keep_c = sh.keep_c;
 
-    const StripItem it = items[w0 + blockIdx.x];
-    const CavityDesc c = a.desc[it.cav];
     const int lane = threadIdx.x;
     const int nx = c.nx, ny = c.ny;
     const int i = it.i0 - kHaloCols + lane;
     const bool in_grid = i >= 0 && i < nx;
     const bool out_col = i >= it.i0 && i < it.i1;
-    const bool lo = i == 1, hi = i == nx - 2;
     const bool walls_b = it.i0 <= 2 || it.i1 >= nx - 2;
     const bool walls_c = it.i0 == 0 || it.i1 == nx;
-    const T dt = T(c.dt), half_dt = T(0.5) * dt, eps = T(c.mix), ulid = T(c.u_lid);
-    const T inv2dxi = T(c.inv2dxi), inv2deta = T(c.inv2deta);
+    const T dt = T(c.dt), half_dt = T(0.5) * dt, eps = T(c.mix), ome = T(1) - T(c.mix), ulid = T(c.u_lid);
+    const T inv2deta = T(c.inv2deta);
+    const T inv2dxi = T(c.inv2dxi);
 
     const auto* fin = static_cast<const typename S::F*>(a.f_in);
     const auto* lin = static_cast<const typename S::L*>(a.l_in);
     auto* fout = static_cast<typename S::F*>(a.f_out);
     auto* lout = static_cast<typename S::L*>(a.l_out);
     const T* geo = geo_of<T>(a);
+    const int64_t col = c.f_off + (in_grid ? i : 0);
+    const int64_t lcol = c.l_off + (in_grid ? i : 0);
 
     // c_kx - c_ky s_i: the contravariant xi-velocity is a_j times this (Eqs. 3.2-3.8.2)
     const T s = in_grid ? geo[c.geo_off + ny + i] : T(0);
-    T dk[9];
-    bool pos[9];
+    T adk[9];
+    bool pos[9], edge[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-        dk[k] = in_grid ? T(cxk(k)) - T(cyk(k)) * s : T(0);
-        pos[k] = dk[k] >= T(0);
+        const T d = in_grid ? T(cxk(k)) - T(cyk(k)) * s : T(0);
+        pos[k] = d >= T(0);
+        adk[k] = pos[k] ? d : -d;
+        edge[k] = pos[k] ? (i == 1) : (i == nx - 2);
     }
 
-    T gbp[5][9], ghp[5][9], fh[5][9], lamr[5], mom[5][3];
-    T fbprev[9], gprev[9], mom0[3] = {0, 0, 0};
+    T gbp[5][9], fh[5][9], lamr[5];
 #pragma unroll
     for (int r = 0; r < 5; ++r) {
         lamr[r] = T(1);
 #pragma unroll
-        for (int k = 0; k < 9; ++k) gbp[r][k] = ghp[r][k] = fh[r][k] = T(0);
-#pragma unroll
-        for (int q = 0; q < 3; ++q) mom[r][q] = T(0);
+        for (int k = 0; k < 9; ++k) gbp[r][k] = fh[r][k] = T(0);
     }
-#pragma unroll
-    for (int k = 0; k < 9; ++k) fbprev[k] = gprev[k] = T(0);
-    double acc[kPartials] = {0, 0, 0, 0, 0, 0, 0};
+    T mom0[3] = {0, 0, 0};
 
     const int j0 = it.j0, j1 = it.j1;
     const int qlo = max(j0 - 2, 0), qhi = min(j1 + 1, ny - 1);
-    const int t_begin = max(j0 - 4, 0), t_end = j1 + 3;
+    const int t_begin = max(j0 - 4, 0), t_end = j1 + 3, t_last = min(t_end, ny - 1);
+
+    // row t_begin, fetched ahead of the loop
+    T gn_[9], ln_ = T(1);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) gn_[k] = in_grid ? S::load(fin, col + k * c.plane + (int64_t)t_begin * c.pitch, k) : T(0);
+    if (in_grid) ln_ = T(lin[lcol + (int64_t)t_begin * c.pitch]);
 
 #pragma unroll 1
     for (int t = t_begin; t <= t_end; ++t) {
+        T g[9], lam_old = ln_;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) g[k] = gn_[k];
+        // fetch row t + 1 now; it is consumed in the next iteration
+        if (t + 1 <= t_last) {
+            const int64_t o = (int64_t)(t + 1) * c.pitch;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) gn_[k] = in_grid ? S::load(fin, col + k * c.plane + o, k) : T(0);
+            if (in_grid) ln_ = T(lin[lcol + o]);
+        }
+        // f-hat of row t - 4 for stage C (read 4 rows ago, now an L2 hit)
+        const int p = t - 4;
+        const bool do_c = p >= j0 && p < j1;
+        T gc[9];
+        if (do_c) {
+            const int64_t o = (int64_t)p * c.pitch;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) gc[k] = in_grid ? S::load(fin, col + k * c.plane + o, k) : T(0);
+        }
+
         // ---------------------------------------------------------- A: row t
         if (t <= ny - 1) {
-            T g[9], lo_lam = T(1);
-            const int64_t node = (int64_t)t * c.pitch + i;
-#pragma unroll
-            for (int k = 0; k < 9; ++k) g[k] = in_grid ? S::load(fin, c.f_off + k * c.plane + node, k) : T(0);
-            if (in_grid) lo_lam = T(lin[c.l_off + node]);
             T P, ux, uy, e[9];
             moments(g, P, ux, uy);
             equilibrium(P, ux, uy, e);
-            const T lam = relaxation_time(g, e, lo_lam, c);
-            const Collision<T> col(lam, dt);
+            const T lam = relaxation_time(g, e, lam_old, c);
+            const Collision<T> coll(lam, dt);
 #pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                gbp[4][k] = col.a_bar * g[k] + col.b_bar * e[k];
-                ghp[4][k] = col.a_hat * g[k] + col.b_hat * e[k];
-            }
+            for (int k = 0; k < 9; ++k) gbp[4][k] = coll.a_bar * g[k] + coll.b_bar * e[k];
             lamr[4] = lam;
-            mom[4][0] = P;
-            mom[4][1] = ux;
-            mom[4][2] = uy;
         }
 
         // ---------------------------------------------------------- B: row t - 2
@@ -205,7 +251,8 @@ __global__ __launch_bounds__(kWaveLanes) void k_fused(StepArgs a, const StripIte
             T fb[9];
             if (q >= 1 && q <= ny - 2) {
                 const T sx = geo[c.geo_off + q] * inv2dxi;
-                transport_row(xs, lane, gbp, gbp[2], dk, pos, lo, hi, q == 1, q == ny - 2, sx, inv2deta, half_dt, eps, fb);
+                transport_row<T, EDGE>(xs, lane, gbp, gbp[2], adk, pos, edge, q == 1, q == ny - 2, sx, inv2deta, half_dt,
+                                       eps, ome, fb);
                 if (walls_b) {
                     publish(wb, i, nx, fb);
                     __syncthreads();
@@ -225,10 +272,12 @@ __global__ __launch_bounds__(kWaveLanes) void k_fused(StepArgs a, const StripIte
                 }
                 if (q == ny - 2)
 #pragma unroll
-                    for (int k = 0; k < 9; ++k) fbprev[k] = fb[k];
+                    for (int k = 0; k < 9; ++k) keep_b[k][lane] = fb[k];
             } else if (q == ny - 1) {   // lid row from row ny - 2
-                T src[9];
-                wall_source(wb, i, nx, fbprev, src);
+                T own[9], src[9];
+#pragma unroll
+                for (int k = 0; k < 9; ++k) own[k] = keep_b[k][lane];
+                wall_source(wb, i, nx, own, src);
                 extrapolate(src, ulid, fb);
             }
             if (q >= 1) {
@@ -240,14 +289,20 @@ __global__ __launch_bounds__(kWaveLanes) void k_fused(StepArgs a, const StripIte
         }
 
         // ---------------------------------------------------------- C: row t - 4
-        const int p = t - 4;
-        if (p >= j0 && p < j1) {
-            const int64_t node = (int64_t)p * c.pitch + i;
-            if (out_col) lout[c.l_off + node] = (typename S::L)lamr[0];
+        if (do_c) {
+            const int64_t node = (int64_t)p * c.pitch;
+            if (out_col) lout[lcol + node] = (typename S::L)lamr[0];
+            T old[3];
+            moments(gc, old[0], old[1], old[2]);
             if (p >= 1 && p <= ny - 2) {
-                T gn[9];
+                // f-hat+ of row p (Eq. 2.15) from its f-hat and the lambda of stage A
+                T e[9], hp[9], gn[9];
+                equilibrium(old[0], old[1], old[2], e);
+                const Collision<T> coll(lamr[0], dt);
+#pragma unroll
+                for (int k = 0; k < 9; ++k) hp[k] = coll.a_hat * gc[k] + coll.b_hat * e[k];
                 const T sx = geo[c.geo_off + p] * inv2dxi;
-                transport_row(xs, lane, fh, ghp[0], dk, pos, lo, hi, p == 1, p == ny - 2, sx, inv2deta, dt, eps, gn);
+                transport_row<T, EDGE>(xs, lane, fh, hp, adk, pos, edge, p == 1, p == ny - 2, sx, inv2deta, dt, eps, ome, gn);
                 if (walls_c) {
                     publish(wc, i, nx, gn);
                     __syncthreads();
@@ -259,8 +314,8 @@ __global__ __launch_bounds__(kWaveLanes) void k_fused(StepArgs a, const StripIte
                 }
                 if (out_col) {
 #pragma unroll
-                    for (int k = 0; k < 9; ++k) S::store(fout, c.f_off + k * c.plane + node, k, gn[k]);
-                    if (RES) residual_add(gn, mom[0], acc);
+                    for (int k = 0; k < 9; ++k) S::store(fout, col + k * c.plane + node, k, gn[k]);
+                    if (RES) residual_add(gn, old, acc);
                 }
                 if (p == 1 && j0 == 0) {   // bottom wall row from row 1
                     T src[9], g0[9];
@@ -268,25 +323,27 @@ __global__ __launch_bounds__(kWaveLanes) void k_fused(StepArgs a, const StripIte
                     extrapolate(src, T(0), g0);
                     if (out_col) {
 #pragma unroll
-                        for (int k = 0; k < 9; ++k) S::store(fout, c.f_off + k * c.plane + i, k, g0[k]);
+                        for (int k = 0; k < 9; ++k) S::store(fout, col + k * c.plane, k, g0[k]);
                         if (RES) residual_add(g0, mom0, acc);
                     }
                 }
                 if (p == ny - 2)
 #pragma unroll
-                    for (int k = 0; k < 9; ++k) gprev[k] = gn[k];
+                    for (int k = 0; k < 9; ++k) keep_c[k][lane] = gn[k];
             } else if (p == ny - 1) {   // lid row from row ny - 2
-                T src[9], gn[9];
-                wall_source(wc, i, nx, gprev, src);
+                T own[9], src[9], gn[9];
+#pragma unroll
+                for (int k = 0; k < 9; ++k) own[k] = keep_c[k][lane];
+                wall_source(wc, i, nx, own, src);
                 extrapolate(src, ulid, gn);
                 if (out_col) {
 #pragma unroll
-                    for (int k = 0; k < 9; ++k) S::store(fout, c.f_off + k * c.plane + node, k, gn[k]);
-                    if (RES) residual_add(gn, mom[0], acc);
+                    for (int k = 0; k < 9; ++k) S::store(fout, col + k * c.plane + node, k, gn[k]);
+                    if (RES) residual_add(gn, old, acc);
                 }
             } else {   // p == 0: stored with row 1; keep its old moments
 #pragma unroll
-                for (int q3 = 0; q3 < 3; ++q3) mom0[q3] = mom[0][q3];
+                for (int m = 0; m < 3; ++m) mom0[m] = old[m];
             }
         }
 
@@ -297,14 +354,25 @@ __global__ __launch_bounds__(kWaveLanes) void k_fused(StepArgs a, const StripIte
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
                 gbp[r][k] = gbp[r + 1][k];
-                ghp[r][k] = ghp[r + 1][k];
                 fh[r][k] = fh[r + 1][k];
             }
-#pragma unroll
-            for (int q3 = 0; q3 < 3; ++q3) mom[r][q3] = mom[r + 1][q3];
         }
     }
+}
 
+template <int PREC, bool RES>
+__global__ __launch_bounds__(kWaveLanes) void k_fused(StepArgs a, const StripItem* items, int w0, int nw)
+{
+    const int w = w0 + xcd_order(blockIdx.x, nw);
+    const StripItem it = items[w];
+    const CavityDesc c = a.desc[it.cav];
+    __shared__ WaveLds<typename Storage<PREC>::T> sh;
+    double acc[kPartials] = {0, 0, 0, 0, 0, 0, 0};
+    // waves that hold column 1 or nx-2 take the first-order one-sided points (Eq. 2.7 at walls)
+    if (it.i0 <= 5 || it.i1 >= c.nx - 5)
+        fused_item<PREC, RES, true>(a, it, c, sh, acc);
+    else
+        fused_item<PREC, RES, false>(a, it, c, sh, acc);
     if (RES) {
         // wavefront sum in a fixed order
 #pragma unroll
@@ -312,7 +380,7 @@ __global__ __launch_bounds__(kWaveLanes) void k_fused(StepArgs a, const StripIte
             double v = acc[q5];
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWaveLanes);
-            if (lane == 0) a.partial[(int64_t)(w0 + blockIdx.x) * kPartials + q5] = v;
+            if (threadIdx.x == 0) a.partial[(int64_t)w * kPartials + q5] = v;
         }
     }
 }
@@ -322,9 +390,9 @@ hipError_t fused(const StepArgs& a, const StripItem* items, int w0, int nw, bool
 {
     if (nw <= 0) return hipSuccess;
     if (residual)
-        hipLaunchKernelGGL((k_fused<PREC, true>), dim3(nw), dim3(kWaveLanes), 0, s, a, items, w0);
+        hipLaunchKernelGGL((k_fused<PREC, true>), dim3(nw), dim3(kWaveLanes), 0, s, a, items, w0, nw);
     else
-        hipLaunchKernelGGL((k_fused<PREC, false>), dim3(nw), dim3(kWaveLanes), 0, s, a, items, w0);
+        hipLaunchKernelGGL((k_fused<PREC, false>), dim3(nw), dim3(kWaveLanes), 0, s, a, items, w0, nw);
     return hipGetLastError();
 }
 
@@ -336,6 +404,7 @@ hipError_t launch_fused_step(int prec, const StepArgs& a, const StripItem* items
     case P_FP64: return fused<P_FP64>(a, items, w0, nw, residual, s);
     case P_FP32: return fused<P_FP32>(a, items, w0, nw, residual, s);
     case P_FP16DEV: return fused<P_FP16DEV>(a, items, w0, nw, residual, s);
+    case P_FP32X: return fused<P_FP32X>(a, items, w0, nw, residual, s);
     }
     return hipErrorInvalidValue;
 }

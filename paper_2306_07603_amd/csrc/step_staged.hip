@@ -251,6 +251,7 @@ hipError_t launch_staged_step(int prec, const StepArgs& a, const NodeBlock* bloc
     case P_FP64: return staged<P_FP64>(a, blocks, b0, nb, residual, s);
     case P_FP32: return staged<P_FP32>(a, blocks, b0, nb, residual, s);
     case P_FP16DEV: return staged<P_FP16DEV>(a, blocks, b0, nb, residual, s);
+    case P_FP32X: return staged<P_FP32X>(a, blocks, b0, nb, residual, s);
     }
     return hipErrorInvalidValue;
 }

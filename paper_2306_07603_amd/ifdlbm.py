@@ -29,11 +29,12 @@ IFDLBM_EDEVICE = -3
 IFDLBM_EDIVERGED = -4
 IFDLBM_ENOTCONVERGED = -5
 
-IFDLBM_FP64, IFDLBM_FP32, IFDLBM_FP16DEV = 0, 1, 2
+IFDLBM_FP64, IFDLBM_FP32, IFDLBM_FP16DEV, IFDLBM_FP32X = 0, 1, 2, 3
 IFDLBM_KERNEL_FUSED, IFDLBM_KERNEL_STAGED = 0, 1
+IFDLBM_DT_CONTRAVARIANT, IFDLBM_DT_CARTESIAN = 0, 1
 IFDLBM_STATUS_RUNNING, IFDLBM_STATUS_CONVERGED, IFDLBM_STATUS_DIVERGED, IFDLBM_STATUS_NOT_CONVERGED = 0, 1, 2, 3
 
-PRECISIONS = {"fp64": IFDLBM_FP64, "fp32": IFDLBM_FP32, "fp16dev": IFDLBM_FP16DEV}
+PRECISIONS = {"fp64": IFDLBM_FP64, "fp32": IFDLBM_FP32, "fp16dev": IFDLBM_FP16DEV, "fp32x": IFDLBM_FP32X}
 KERNELS = {"fused": IFDLBM_KERNEL_FUSED, "staged": IFDLBM_KERNEL_STAGED}
 
 
@@ -52,7 +53,7 @@ class ifdlbm_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("cfl", ctypes.c_double), ("mix", ctypes.c_double),
                 ("rho0", ctypes.c_double), ("gamma_min", ctypes.c_double), ("residual_every", ctypes.c_int32),
                 ("kernel", ctypes.c_int32), ("batched", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
-                ("hip_stream", ctypes.c_void_p)]
+                ("dt_rule", ctypes.c_int32), ("hip_stream", ctypes.c_void_p)]
 
 
 class ifdlbm_info_t(ctypes.Structure):
@@ -88,6 +89,8 @@ def lib():
         L.ifdlbm_set_state.argtypes = [_H, ctypes.c_int32, _D, _D]
         L.ifdlbm_status.argtypes = [_H, ctypes.c_int32]
         L.ifdlbm_info.argtypes = [_H, ctypes.POINTER(ifdlbm_info_t)]
+        L.ifdlbm_gradient.argtypes = [ctypes.POINTER(ifdlbm_cavity), ctypes.POINTER(ifdlbm_options), ctypes.c_int64,
+                                      ctypes.c_int32, _D, _D]
         L.ifdlbm_destroy.argtypes = [_H]
         L.ifdlbm_destroy.restype = None
         L.ifdlbm_strerror.argtypes = [ctypes.c_int]
@@ -243,6 +246,20 @@ def ifdlbm_info(h: Handle) -> dict:
     i = ifdlbm_info_t()
     _check(lib().ifdlbm_info(h.ptr, ctypes.byref(i)))
     return {k: getattr(i, k) for k, _ in ifdlbm_info_t._fields_}
+
+
+IFDLBM_OBJ_KINETIC_ENERGY = 0
+
+
+def ifdlbm_gradient(cavity: Cavity, options: Optional[ifdlbm_options] = None, n_steps: int = 1,
+                    objective: int = IFDLBM_OBJ_KINETIC_ENERGY):
+    """(J, [dJ/dtheta_rad, dJ/dn, dJ/du_lid]) of the objective after n_steps steps."""
+    options = options or ifdlbm_default_options()
+    J = ctypes.c_double()
+    grad = np.zeros(3)
+    _check(lib().ifdlbm_gradient(ctypes.byref(cavity.c()), ctypes.byref(options), int(n_steps), int(objective),
+                                 ctypes.byref(J), _dptr(grad)))
+    return J.value, grad
 
 
 def ifdlbm_destroy(h: Handle) -> None:
