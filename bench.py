@@ -3,9 +3,10 @@
 Workload (one "step" = one time step of every cavity): the seeded batch of
 256 lid-driven isosceles-trapezoid cavities of uneven size and parameters
 (sides 65/129/257/513, Re 100-5000 log-uniform, n 0.5-1.5, theta 40-90 deg,
-lid 0.1, CFL 0.5), FP32 storage and arithmetic, FP64 residual sums of
-Eq. (2.19) every 100 steps, all cavities in one launch per step, replayed
-from a captured HIP graph.  Inputs start resident in HBM (Step 1 on the
+lid 0.1, CFL 0.5), FP32 storage of the distributions with stochastic
+rounding and FP64 arithmetic by default (--precision selects the other
+modes), FP64 residual sums of Eq. (2.19) every 100 steps, all cavities in one
+launch per step, replayed from a captured HIP graph.  Inputs start resident in HBM (Step 1 on the
 device).  Printed on one JSON line: MLUPS, the roofline record of the step
 kernel (algorithmic bytes per launch over its average duration, from HIP
 events on the stream the library launches on), the same batch in FP64 with
@@ -27,8 +28,16 @@ if ROOT not in sys.path:
 METRIC = "MLUPS & % HBM roofline, FP32-batched vs plain FP64 on GPU at ≤1e-5 vs oracle"
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, published
 WORKLOAD = ("256-cavity uneven batch: sides {65,129,257,513}, Re log-uniform [100,5000], n uniform [0.5,1.5], "
-            "theta uniform [40,90] deg, lid 0.1, CFL 0.5; FP32 storage, FP64 residual sums every 100 steps, "
+            "theta uniform [40,90] deg, lid 0.1, CFL 0.5; FP64 residual sums every 100 steps, "
             "one launch per step, HIP-graph replay")
+# storage of the distributions and arithmetic type of each precision mode
+PRECISION = {
+    "fp32sr": ("FP32, stochastic rounding", "f64"),
+    "fp32": ("FP32, round to nearest", "f32"),
+    "fp32x": ("FP32, round to nearest", "f64"),
+    "fp16dev": ("FP16 of g_k / w_k", "f32"),
+    "fp64": ("FP64", "f64"),
+}
 
 
 def log(msg: str) -> None:
@@ -71,17 +80,37 @@ def cpu_baseline(specs, steps: int):
                       "%.1f s" % (steps, dt)}
 
 
+def copy_calibration() -> int:
+    """A device-to-device copy of 2 GiB, three times: under rocprofv3 --pmc the
+    FETCH_SIZE and WRITE_SIZE counters of a copy of known size give the scale
+    from counter units to bytes on this device."""
+    import torch
+    n = (2 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 4, "copies": 3}))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--kernel", default="fused", choices=["fused", "staged"])
+    ap.add_argument("--precision", default="fp32sr", choices=["fp32sr", "fp32", "fp32x", "fp16dev", "fp64"])
     ap.add_argument("--residual-every", type=int, default=100)
     ap.add_argument("--graph-steps", type=int, default=100)
     ap.add_argument("--plain-steps", type=int, default=100, help="steps of the plain FP64 comparison run (0: skip)")
-    ap.add_argument("--cpu-steps", type=int, default=20, help="steps of the CPU oracle sample (0: skip)")
+    ap.add_argument("--cpu-steps", type=int, default=100, help="steps of the CPU oracle sample (0: skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 2 GiB device copy three times (scale for the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (cavities are independent; "
               "the batch would shard across GPUs with no communication).", file=sys.stderr)
@@ -100,7 +129,7 @@ def main() -> int:
     specs = W.batch_sweep()
     cav = [M.Cavity(**s.__dict__) for s in specs]
 
-    opt = M.ifdlbm_default_options(precision="fp32", kernel=args.kernel, residual_every=args.residual_every,
+    opt = M.ifdlbm_default_options(precision=args.precision, kernel=args.kernel, residual_every=args.residual_every,
                                    graph_steps=args.graph_steps, batched=1, hip_stream=stream.cuda_stream)
     h = M.ifdlbm_create(cav, opt)
     info = M.ifdlbm_info(h)
@@ -117,7 +146,7 @@ def main() -> int:
     kernel_ms = ev_ms / launches
     alg_bytes = nodes * info["alg_bytes_per_node"]
     achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
-    log("fp32 batched: %.1f MLUPS, %.3f ms/step, kernel %.3f ms, %.0f GB/s" % (mlups, wall * 1e3 / args.steps, kernel_ms, achieved))
+    log(args.precision + " batched: %.1f MLUPS, %.3f ms/step, kernel %.3f ms, %.0f GB/s" % (mlups, wall * 1e3 / args.steps, kernel_ms, achieved))
     h.close()
 
     plain = None
@@ -139,8 +168,9 @@ def main() -> int:
     out = {
         "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
+        "dtype": PRECISION[args.precision][1], "data": "synthetic",
         "config": {"workload": WORKLOAD, "cavities": len(specs), "nodes_per_step": nodes, "kernel": args.kernel,
+                   "precision": args.precision, "storage": PRECISION[args.precision][0],
                    "diverged_cavities": diverged,
                    "residual_every": args.residual_every, "graph_steps": args.graph_steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -56,6 +56,8 @@ typedef struct ifdlbm_s ifdlbm_t;
 #define IFDLBM_FP16DEV  2   /* FP16 scaled deviations (f-hat - omega_k rho0)/omega_k, FP32 lambda
                                and FP32 arithmetic                                                 */
 #define IFDLBM_FP32X    3   /* FP32 deviations and lambda in memory, FP64 arithmetic               */
+#define IFDLBM_FP32SR   4   /* as FP32X, the deviations stored with stochastic rounding (unbiased:
+                               no constant forcing of a steady state by the rounding)             */
 
 /* kernel schedule (options.kernel) */
 #define IFDLBM_KERNEL_FUSED    0   /* one fused launch per step (default)                        */
@@ -83,7 +85,7 @@ typedef struct {
 } ifdlbm_cavity;
 
 typedef struct {
-    int32_t precision;      /* IFDLBM_FP64 | IFDLBM_FP32 | IFDLBM_FP16DEV | IFDLBM_FP32X              */
+    int32_t precision;      /* IFDLBM_FP64 | _FP32 | _FP16DEV | _FP32X | _FP32SR                       */
     double  cfl;            /* Courant number, > 0 (paper: 0.5); dt follows dt_rule                   */
     double  mix;            /* weight of the central scheme in Eq. (2.5), [0, 1] (default 0.5)       */
     double  rho0;           /* constant density of Eq. (2.8) (default 1); u and P do not depend on it */

@@ -41,7 +41,7 @@ int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
 size_t f_elem_size(int prec) { return prec == P_FP64 ? 8 : (prec == P_FP16DEV ? 2 : 4); }
 size_t l_elem_size(int prec) { return prec == P_FP64 ? 8 : 4; }
-size_t t_elem_size(int prec) { return (prec == P_FP64 || prec == P_FP32X) ? 8 : 4; }
+size_t t_elem_size(int prec) { return (prec == P_FP64 || prec == P_FP32X || prec == P_FP32SR) ? 8 : 4; }
 
 // 1/tan(theta) with theta in degrees; exactly 0 for the square.
 double cot_deg(double theta_deg)
@@ -83,6 +83,7 @@ struct ifdlbm_s {
     double* d_partial = nullptr;
     double* d_res = nullptr;                        // n_cav * kPartials
     double* d_scratch = nullptr;                    // 10 * max nodes doubles
+    uint32_t* d_seed = nullptr;                     // stochastic-rounding step counter
     size_t scratch_elems = 0;
 
     std::vector<int> status;
@@ -153,13 +154,17 @@ StepArgs step_args(ifdlbm_s* h)
     a.bar_plus = h->d_bp;
     a.bar_half = h->d_fb;
     a.lam_new = h->d_ln;
+    a.seed_ctr = h->d_seed;
+    a.step = 0;
     return a;
 }
 
-// Enqueue one time step of the running cavities, reading buffer `cur`.
-int enqueue_step(ifdlbm_s* h, bool residual)
+// Enqueue one time step of the running cavities, reading buffer `cur`;
+// `local` numbers the step within its call or graph (stochastic rounding).
+int enqueue_step(ifdlbm_s* h, bool residual, uint32_t local)
 {
-    const StepArgs a = step_args(h);
+    StepArgs a = step_args(h);
+    a.step = local;
     const int prec = h->opt.precision;
     const bool staged = h->opt.kernel == IFDLBM_KERNEL_STAGED;
     hipError_t e = hipSuccess;
@@ -183,8 +188,12 @@ bool is_residual_step(const ifdlbm_s* h, int64_t step_index) { return (step_inde
 
 int eager_steps(ifdlbm_s* h, int64_t n)
 {
+    if (n > 0) {
+        hipError_t e = launch_seed_bump(h->d_seed, h->stream);
+        if (e != hipSuccess) return fail(IFDLBM_EDEVICE, std::string("seed: ") + hipGetErrorString(e));
+    }
     for (int64_t s = 0; s < n; ++s) {
-        int rc = enqueue_step(h, is_residual_step(h, h->step_count));
+        int rc = enqueue_step(h, is_residual_step(h, h->step_count), (uint32_t)s);
         if (rc) return rc;
         h->cur ^= 1;
         h->step_count++;
@@ -207,8 +216,9 @@ int build_graph(ifdlbm_s* h)
     hipGraph_t graph = nullptr;
     IFD_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
     int rc = IFDLBM_OK;
+    if (launch_seed_bump(h->d_seed, h->stream) != hipSuccess) rc = fail(IFDLBM_EDEVICE, "seed bump in capture");
     for (int s = 0; s < G && rc == IFDLBM_OK; ++s) {
-        rc = enqueue_step(h, is_residual_step(h, s));
+        rc = enqueue_step(h, is_residual_step(h, s), (uint32_t)s);
         h->cur ^= 1;
     }
     hipError_t e = hipStreamEndCapture(h->stream, &graph);
@@ -295,7 +305,7 @@ void free_all(ifdlbm_s* h)
     if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
     void* ptrs[] = {h->d_f[0], h->d_f[1], h->d_l[0], h->d_l[1], h->d_desc, h->d_geo, h->d_geo32, h->d_hp, h->d_bp,
                     h->d_fb, h->d_ln, h->d_all_blocks, h->d_act_blocks, h->d_act_items, h->d_unit_first,
-                    h->d_unit_count, h->d_partial, h->d_res, h->d_scratch};
+                    h->d_unit_count, h->d_partial, h->d_res, h->d_scratch, h->d_seed};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -341,7 +351,7 @@ int ifdlbm_create(const ifdlbm_cavity* cav, int32_t n_cav, const ifdlbm_options*
     *out = nullptr;
     if (!cav || !opt || n_cav <= 0) return fail(IFDLBM_EINVAL, "need at least one cavity and options");
     const ifdlbm_options& o = *opt;
-    if (o.precision < IFDLBM_FP64 || o.precision > IFDLBM_FP32X) return fail(IFDLBM_EINVAL, "unknown precision");
+    if (o.precision < IFDLBM_FP64 || o.precision > IFDLBM_FP32SR) return fail(IFDLBM_EINVAL, "unknown precision");
     if (!(o.cfl > 0.0) || !(o.mix >= 0.0 && o.mix <= 1.0) || !(o.gamma_min > 0.0) || !std::isfinite(o.rho0))
         return fail(IFDLBM_EINVAL, "cfl must be > 0, mix in [0, 1], gamma_min > 0, rho0 finite");
     if (o.residual_every < 1) return fail(IFDLBM_EINVAL, "residual_every must be >= 1");
@@ -353,8 +363,9 @@ int ifdlbm_create(const ifdlbm_cavity* cav, int32_t n_cav, const ifdlbm_options*
         const ifdlbm_cavity& v = cav[c];
         const std::string id = "cavity " + std::to_string(c) + ": ";
         if (v.n_xi < 5 || v.n_eta < 5) return fail(IFDLBM_EINVAL, id + "n_xi and n_eta must be >= 5");
-        if (v.n_xi > 32767 || (int64_t)v.n_xi * v.n_eta > (int64_t)1 << 30)
-            return fail(IFDLBM_EINVAL, id + "grid too large (n_xi <= 32767, n_xi * n_eta <= 2^30)");
+        // 32-bit byte offsets inside a plane: n_eta * pitch * 8 < 2^31
+        if (v.n_xi > 32767 || (int64_t)((v.n_xi + 15) / 16 * 16) * v.n_eta > (int64_t)1 << 28)
+            return fail(IFDLBM_EINVAL, id + "grid too large (n_xi <= 32767, n_eta * n_xi <= 2^28)");
         if (!(v.theta_deg > 0.0 && v.theta_deg <= 90.0)) return fail(IFDLBM_EINVAL, id + "theta_deg must be in (0, 90]");
         if (!(v.n > 0.0) || !std::isfinite(v.n)) return fail(IFDLBM_EINVAL, id + "n must be > 0");
         if (!(v.re > 0.0) || !std::isfinite(v.re)) return fail(IFDLBM_EINVAL, id + "re must be > 0");
@@ -460,6 +471,7 @@ int ifdlbm_create(const ifdlbm_cavity* cav, int32_t n_cav, const ifdlbm_options*
     if (!rc) rc = dalloc(&h->d_partial, h->max_units * kPartials * sizeof(double));
     if (!rc) rc = dalloc(&h->d_res, (size_t)n_cav * kPartials * sizeof(double));
     if (!rc) rc = dalloc(&h->d_scratch, h->scratch_elems * sizeof(double));
+    if (!rc) rc = dalloc(&h->d_seed, sizeof(uint32_t));
     if (rc) return bail(rc);
 
     std::vector<float> geo32(geo.begin(), geo.end());
@@ -471,6 +483,7 @@ int ifdlbm_create(const ifdlbm_cavity* cav, int32_t n_cav, const ifdlbm_options*
     if (e == hipSuccess) e = copy(h->d_all_blocks, h->all_blocks.data(), h->all_blocks.size() * sizeof(NodeBlock));
     if (e == hipSuccess) e = copy(h->d_desc, h->desc.data(), n_cav * sizeof(CavityDesc));
     if (e == hipSuccess) e = hipMemsetAsync(h->d_res, 0, (size_t)n_cav * kPartials * sizeof(double), h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(h->d_seed, 0, sizeof(uint32_t), h->stream);
     if (e == hipSuccess)
         e = launch_init(prec, h->d_f[0], h->d_l[0], h->d_desc, h->d_all_blocks, (int)h->all_blocks.size(), h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);

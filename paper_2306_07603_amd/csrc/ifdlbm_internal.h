@@ -53,7 +53,13 @@ struct StepArgs {
     void* bar_plus;          // f-bar+ (Eq. 2.16), then f(t + dt/2) (Eq. 2.17), 9 planes
     void* bar_half;          // f-bar(t + dt/2) (Eq. 3.7), 9 planes
     void* lam_new;           // lambda of this step
+    // stochastic rounding: seed of this launch = mix of *seed_ctr and step
+    const uint32_t* seed_ctr;
+    uint32_t step;
 };
+
+// Advance the device seed counter by one (a one-thread kernel, graph-safe).
+hipError_t launch_seed_bump(uint32_t* ctr, hipStream_t s);
 
 // Staged schedule: five launches per step over the node blocks
 // [b0, b0 + nb), plus the residual launch when `residual` is set.

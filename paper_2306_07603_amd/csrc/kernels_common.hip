@@ -134,6 +134,8 @@ __global__ __launch_bounds__(256) void k_energy(const void* fv, CavityDesc c, do
     if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
 }
 
+__global__ void k_seed_bump(uint32_t* ctr) { ctr[0] += 1u; }
+
 inline unsigned blocks_of(const CavityDesc& c) { return (unsigned)((c.nx * c.ny + 255) / 256); }
 
 }  // namespace
@@ -146,8 +148,15 @@ hipError_t launch_init(int prec, void* f, void* l, const CavityDesc* desc, const
     case P_FP32: hipLaunchKernelGGL(k_init<P_FP32>, dim3(nb), dim3(kNodeBlock), 0, s, f, l, desc, blocks); break;
     case P_FP16DEV: hipLaunchKernelGGL(k_init<P_FP16DEV>, dim3(nb), dim3(kNodeBlock), 0, s, f, l, desc, blocks); break;
     case P_FP32X: hipLaunchKernelGGL(k_init<P_FP32X>, dim3(nb), dim3(kNodeBlock), 0, s, f, l, desc, blocks); break;
+    case P_FP32SR: hipLaunchKernelGGL(k_init<P_FP32SR>, dim3(nb), dim3(kNodeBlock), 0, s, f, l, desc, blocks); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_seed_bump(uint32_t* ctr, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_seed_bump, dim3(1), dim3(1), 0, s, ctr);
     return hipGetLastError();
 }
 
@@ -173,6 +182,7 @@ hipError_t launch_fields(int prec, const void* f, const CavityDesc*, int, const 
     case P_FP32: IFD_FIELDS(P_FP32) break;
     case P_FP16DEV: IFD_FIELDS(P_FP16DEV) break;
     case P_FP32X: IFD_FIELDS(P_FP32X) break;
+    case P_FP32SR: IFD_FIELDS(P_FP32SR) break;
     default: return hipErrorInvalidValue;
     }
 #undef IFD_FIELDS
@@ -188,6 +198,7 @@ hipError_t launch_state_out(int prec, const void* f, const void* l, const Cavity
     case P_FP32: hipLaunchKernelGGL(k_state_out<P_FP32>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
     case P_FP16DEV: hipLaunchKernelGGL(k_state_out<P_FP16DEV>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
     case P_FP32X: hipLaunchKernelGGL(k_state_out<P_FP32X>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
+    case P_FP32SR: hipLaunchKernelGGL(k_state_out<P_FP32SR>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -202,6 +213,7 @@ hipError_t launch_state_in(int prec, void* f, void* l, const CavityDesc& hd, dou
     case P_FP32: hipLaunchKernelGGL(k_state_in<P_FP32>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
     case P_FP16DEV: hipLaunchKernelGGL(k_state_in<P_FP16DEV>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
     case P_FP32X: hipLaunchKernelGGL(k_state_in<P_FP32X>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
+    case P_FP32SR: hipLaunchKernelGGL(k_state_in<P_FP32SR>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -216,6 +228,7 @@ hipError_t launch_energy(int prec, const void* f, const CavityDesc*, const doubl
     case P_FP32: hipLaunchKernelGGL(k_energy<P_FP32>, g, b, 0, s, f, hd, partial); break;
     case P_FP16DEV: hipLaunchKernelGGL(k_energy<P_FP16DEV>, g, b, 0, s, f, hd, partial); break;
     case P_FP32X: hipLaunchKernelGGL(k_energy<P_FP32X>, g, b, 0, s, f, hd, partial); break;
+    case P_FP32SR: hipLaunchKernelGGL(k_energy<P_FP32SR>, g, b, 0, s, f, hd, partial); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -15,7 +15,41 @@
 
 namespace ifd {
 
-enum Precision { P_FP64 = 0, P_FP32 = 1, P_FP16DEV = 2, P_FP32X = 3 };
+enum Precision { P_FP64 = 0, P_FP32 = 1, P_FP16DEV = 2, P_FP32X = 3, P_FP32SR = 4 };
+
+// ------------------------------------------------------- random bits
+// Integer mixing function (the "lowbias32" finaliser of C. Wellons's hash
+// prospector): a bijection of 32-bit words with good avalanche.
+__host__ __device__ inline uint32_t mix32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// Random word of (step, cavity, node); population k takes mix32(seed + k * golden).
+__device__ inline uint32_t node_seed(uint32_t step, int cav, int j, int i)
+{
+    return mix32(step ^ mix32((uint32_t)cav * 0x9E3779B9u ^ mix32((uint32_t)j * 0x85EBCA6Bu ^ (uint32_t)i)));
+}
+
+__device__ inline uint32_t pop_bits(uint32_t seed, int k) { return mix32(seed + (uint32_t)k * 0x9E3779B9u); }
+
+// Stochastic rounding of an FP64 value to FP32: add 29 random bits below the
+// FP32 mantissa of the FP64 significand and truncate.  The result is the FP32
+// neighbour above (in magnitude) with probability equal to the discarded
+// fraction, so the rounding error has zero mean; the truncated value converts
+// to FP32 exactly (normal range).
+__device__ inline float round_stochastic(double v, uint32_t r)
+{
+    unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    b += (unsigned long long)(r & 0x1FFFFFFFu);
+    b &= ~0x1FFFFFFFull;
+    return (float)__longlong_as_double((long long)b);
+}
 
 // One cavity in the device tables.  Planes are SoA: population k of node
 // (i, j) lives at f_off + k * plane + j * pitch + i.
@@ -46,6 +80,7 @@ struct CavityDesc {
 template <int PREC> struct Storage;
 
 template <> struct Storage<P_FP64> {
+    static constexpr bool kStochastic = false;
     using F = double;   // distribution element
     using L = double;   // lambda element
     using T = double;   // arithmetic
@@ -54,6 +89,7 @@ template <> struct Storage<P_FP64> {
 };
 
 template <> struct Storage<P_FP32> {
+    static constexpr bool kStochastic = false;
     using F = float;
     using L = float;
     using T = float;
@@ -63,6 +99,7 @@ template <> struct Storage<P_FP32> {
 
 // FP32 storage with FP64 arithmetic: only the stored state is rounded to FP32.
 template <> struct Storage<P_FP32X> {
+    static constexpr bool kStochastic = false;
     using F = float;
     using L = float;
     using T = double;
@@ -70,9 +107,33 @@ template <> struct Storage<P_FP32X> {
     __device__ static inline void store(F* p, int64_t i, int, T v) { p[i] = (F)v; }
 };
 
+// FP32 storage, FP64 arithmetic, distributions stored with stochastic
+// rounding: at a steady state the rounding of the stored state no longer acts
+// as a constant forcing (with round-to-nearest it shifts the fixed point).
+template <> struct Storage<P_FP32SR> {
+    static constexpr bool kStochastic = true;
+    using F = float;
+    using L = float;
+    using T = double;
+    __device__ static inline T load(const F* p, int64_t i, int) { return (T)p[i]; }
+    __device__ static inline void store(F* p, int64_t i, int, T v) { p[i] = (F)v; }
+    __device__ static inline void store_sr(F* p, int64_t i, T v, uint32_t r) { p[i] = round_stochastic(v, r); }
+};
+
+// Store of a state population: stochastic rounding where the storage asks for it.
+template <typename S>
+__device__ __forceinline__ void store_state(typename S::F* p, int64_t i, int k, typename S::T v, uint32_t seed)
+{
+    if constexpr (S::kStochastic)
+        S::store_sr(p, i, v, pop_bits(seed, k));
+    else
+        S::store(p, i, k, v);
+}
+
 // FP16 storage of g_k / omega_k: the division by the lattice weight puts all
 // nine planes on the same O(3 P + 3 c.u) scale, inside FP16's normal range.
 template <> struct Storage<P_FP16DEV> {
+    static constexpr bool kStochastic = false;
     using F = __half;
     using L = float;
     using T = float;
@@ -145,10 +206,22 @@ template <> __device__ __forceinline__ float pow_pos<float>(float x, float y)
 // (2 lam_old + dt), so D = (grad u + grad u^T)/2 = -3 Pi / (2 lam_old + dt)
 // with Pi = sum_k c_k c_k (g_k - e_k), and 2 D:D = 18 (Pxx^2 + 2 Pxy^2 + Pyy^2)
 // / (2 lam_old + dt)^2.  mu = K max(2 D:D, gamma_min^2)^((n-1)/2), lambda = mu / c_s^2.
+// The parameters of Step (2) in the arithmetic type, converted once per work item.
 template <typename T>
-__device__ __forceinline__ T relaxation_time(const T g[9], const T e[9], T lam_old, const CavityDesc& c)
+struct PowerLaw {
+    T K3, expo, g2min, dt, lam_newton;
+    bool newtonian;
+    __device__ __forceinline__ explicit PowerLaw(const CavityDesc& c)
+        : K3(T(3) * T(c.K)), expo(T(c.expo)), g2min(T(c.g2min)), dt(T(c.dt)), lam_newton(T(c.lam_newton)),
+          newtonian(c.newtonian != 0)
+    {
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ T relaxation_time(const T g[9], const T e[9], T lam_old, const PowerLaw<T>& pl)
 {
-    if (c.newtonian) return T(c.lam_newton);
+    if (pl.newtonian) return pl.lam_newton;
     T n[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) n[k] = g[k] - e[k];
@@ -156,10 +229,16 @@ __device__ __forceinline__ T relaxation_time(const T g[9], const T e[9], T lam_o
     const T pxx = (n[1] + n[3]) + s58;
     const T pyy = (n[2] + n[4]) + s58;
     const T pxy = (n[5] - n[6]) + (n[7] - n[8]);
-    const T r = recip(T(2) * lam_old + T(c.dt));
+    const T r = recip(T(2) * lam_old + pl.dt);
     T gamma2 = T(18) * (pxx * pxx + T(2) * pxy * pxy + pyy * pyy) * r * r;
-    gamma2 = gamma2 > T(c.g2min) ? gamma2 : T(c.g2min);
-    return T(3) * T(c.K) * pow_pos<T>(gamma2, T(c.expo));
+    gamma2 = gamma2 > pl.g2min ? gamma2 : pl.g2min;
+    return pl.K3 * pow_pos<T>(gamma2, pl.expo);
+}
+
+template <typename T>
+__device__ __forceinline__ T relaxation_time(const T g[9], const T e[9], T lam_old, const CavityDesc& c)
+{
+    return relaxation_time(g, e, lam_old, PowerLaw<T>(c));
 }
 
 // Steps (3)-(4): Eq. (2.15) f-hat+ = ((2 lam - dt) g + 2 dt e) / (2 lam + dt) and

@@ -38,28 +38,34 @@ __device__ __forceinline__ int xcd_order(int b, int nw)
     return x * q + min(x, r) + b / kXcds;
 }
 
-// Eq. (2.5) times sign(c) * 2h from the upwind-side points a1 (one behind)
-// and a2 (two behind) and the point f1 one ahead: sign(c) * central = f1 - a1,
-// sign(c) * upwind = 3 c0 - 4 a1 + a2 (Eqs. 2.6-2.7).  Multiplied by |c| it is
-// c * (eps * central + (1 - eps) * upwind).
+// Weights of Eq. (2.5) times sign(c) * 2h on the upwind-sorted points a2
+// (two behind), a1 (one behind), c0 and f1 (one ahead):
+// sign(c) * central = f1 - a1 (Eq. 2.6), sign(c) * upwind = 3 c0 - 4 a1 + a2
+// (Eq. 2.7), so eps * central + (1 - eps) * upwind is
+// eps f1 - (4 - 3 eps) a1 + 3 (1 - eps) c0 + (1 - eps) a2.
 template <typename T>
-__device__ __forceinline__ T mixed_signed(T a2, T a1, T c0, T f1, T eps, T ome)
-{
-    return eps * (f1 - a1) + ome * ((T(3) * c0 - T(4) * a1) + a2);
-}
+struct MixedWeights {
+    T wf, wa1, wc, wa2;
+    __device__ __forceinline__ explicit MixedWeights(T eps)
+        : wf(eps), wa1(-(T(4) - T(3) * eps)), wc(T(3) * (T(1) - eps)), wa2(T(1) - eps)
+    {
+    }
+    __device__ __forceinline__ T apply(T a2, T a1, T c0, T f1) const { return ((wc * c0 + wa1 * a1) + wa2 * a2) + wf * f1; }
+};
 
 // c_k . grad Phi_k of Eq. (3.4) for the eight moving populations of one row,
-// times `step`, subtracted from `base`:
-//   out[k] = base[k] - step * (sx * |dk[k]| * D_xi + sy * D_eta)
-// with D the signed mixed differences; the xi neighbours come from the LDS
-// row, the eta neighbours from ring slots 0..4 (rows r-2..r+2).  Where the
-// second upwind point would leave the grid (EDGE waves) it is replaced by the
-// linear extrapolation 2 a1 - c0, which gives the first-order difference.
+// times the step, subtracted from `base`:
+//   out[k] = base[k] - sx * |dk[k]| * D_xi - sy * D_eta
+// where sx = step a_j / (2 dxi) and sy = step / (2 deta) and D are the signed
+// mixed differences; the xi neighbours come from the LDS row, the eta
+// neighbours from ring slots 0..4 (rows r-2..r+2).  Where the second upwind
+// point would leave the grid (EDGE waves) it is replaced by the linear
+// extrapolation 2 a1 - c0, which gives the first-order difference.
 template <typename T, bool EDGE>
 __device__ __forceinline__ void transport_row(T (*xs)[kWaveLanes + 2 * kPad], int lane, const T (&ring)[5][9],
                                               const T (&base)[9], const T (&adk)[9], const bool (&pos)[9],
-                                              const bool (&edge)[9], bool lo_eta, bool hi_eta, T sx, T sy, T step,
-                                              T eps, T ome, T (&out)[9])
+                                              const bool (&edge)[9], bool lo_eta, bool hi_eta, T sx, T sy,
+                                              const MixedWeights<T>& w, T (&out)[9])
 {
 #pragma unroll
     for (int k = 1; k < 9; ++k) xs[k - 1][lane + kPad] = ring[2][k];
@@ -75,7 +81,7 @@ __device__ __forceinline__ void transport_row(T (*xs)[kWaveLanes + 2 * kPad], in
         T a2 = pos[k] ? m2 : p2;
         const T f1 = pos[k] ? p1 : m1;
         if (EDGE) a2 = edge[k] ? T(2) * a1 - c0 : a2;
-        T term = sx * adk[k] * mixed_signed(a2, a1, c0, f1, eps, ome);
+        T o = base[k] - (sx * adk[k]) * w.apply(a2, a1, c0, f1);
         if (cyk(k) != 0) {
             // sign of c_k,eta = c_ky is fixed by k
             const bool up = cyk(k) > 0;
@@ -83,9 +89,9 @@ __device__ __forceinline__ void transport_row(T (*xs)[kWaveLanes + 2 * kPad], in
             T e2 = up ? ring[0][k] : ring[4][k];
             const T g1 = up ? ring[3][k] : ring[1][k];
             if ((up && lo_eta) || (!up && hi_eta)) e2 = T(2) * e1 - c0;
-            term += sy * mixed_signed(e2, e1, c0, g1, eps, ome);
+            o = o - sy * w.apply(e2, e1, c0, g1);
         }
-        out[k] = base[k] - step * term;
+        out[k] = o;
     }
     __syncthreads();
 }
@@ -164,29 +170,33 @@ __device__ __forceinline__ void fused_item(const StepArgs& a, const StripItem& i
     const int lane = threadIdx.x;
     const int nx = c.nx, ny = c.ny;
     const int i = it.i0 - kHaloCols + lane;
-    const bool in_grid = i >= 0 && i < nx;
+    // halo lanes outside the grid read the nearest column; their results are never used
+    const int ic = min(max(i, 0), nx - 1);
     const bool out_col = i >= it.i0 && i < it.i1;
     const bool walls_b = it.i0 <= 2 || it.i1 >= nx - 2;
     const bool walls_c = it.i0 == 0 || it.i1 == nx;
-    const T dt = T(c.dt), half_dt = T(0.5) * dt, eps = T(c.mix), ome = T(1) - T(c.mix), ulid = T(c.u_lid);
-    const T inv2deta = T(c.inv2deta);
-    const T inv2dxi = T(c.inv2dxi);
+    const PowerLaw<T> pl(c);
+    const T dt = pl.dt, ulid = T(c.u_lid);
+    const T sy_b = T(0.5) * dt * T(c.inv2deta), sy_c = dt * T(c.inv2deta);
+    const T sx_b = T(0.5) * dt * T(c.inv2dxi), sx_c = dt * T(c.inv2dxi);
+    const MixedWeights<T> mw(T(c.mix));
 
-    const auto* fin = static_cast<const typename S::F*>(a.f_in);
-    const auto* lin = static_cast<const typename S::L*>(a.l_in);
-    auto* fout = static_cast<typename S::F*>(a.f_out);
-    auto* lout = static_cast<typename S::L*>(a.l_out);
-    const T* geo = geo_of<T>(a);
-    const int64_t col = c.f_off + (in_grid ? i : 0);
-    const int64_t lcol = c.l_off + (in_grid ? i : 0);
+    // uniform base of each plane (64-bit, scalar) plus a 32-bit row offset per lane
+    const auto* fin = static_cast<const typename S::F*>(a.f_in) + c.f_off;
+    const auto* lin = static_cast<const typename S::L*>(a.l_in) + c.l_off;
+    auto* fout = static_cast<typename S::F*>(a.f_out) + c.f_off;
+    auto* lout = static_cast<typename S::L*>(a.l_out) + c.l_off;
+    const int64_t plane = c.plane;
+    const T* geo = geo_of<T>(a) + c.geo_off;
+    const uint32_t lseed = S::kStochastic ? mix32(a.seed_ctr[0] ^ mix32(a.step)) : 0u;
 
     // c_kx - c_ky s_i: the contravariant xi-velocity is a_j times this (Eqs. 3.2-3.8.2)
-    const T s = in_grid ? geo[c.geo_off + ny + i] : T(0);
+    const T s = geo[ny + ic];
     T adk[9];
     bool pos[9], edge[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-        const T d = in_grid ? T(cxk(k)) - T(cyk(k)) * s : T(0);
+        const T d = T(cxk(k)) - T(cyk(k)) * s;
         pos[k] = d >= T(0);
         adk[k] = pos[k] ? d : -d;
         edge[k] = pos[k] ? (i == 1) : (i == nx - 2);
@@ -206,10 +216,13 @@ __device__ __forceinline__ void fused_item(const StepArgs& a, const StripItem& i
     const int t_begin = max(j0 - 4, 0), t_end = j1 + 3, t_last = min(t_end, ny - 1);
 
     // row t_begin, fetched ahead of the loop
-    T gn_[9], ln_ = T(1);
+    T gn_[9], ln_;
+    {
+        const uint32_t o = (uint32_t)(t_begin * c.pitch + ic);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) gn_[k] = in_grid ? S::load(fin, col + k * c.plane + (int64_t)t_begin * c.pitch, k) : T(0);
-    if (in_grid) ln_ = T(lin[lcol + (int64_t)t_begin * c.pitch]);
+        for (int k = 0; k < 9; ++k) gn_[k] = S::load(fin + k * plane, o, k);
+        ln_ = T(lin[o]);
+    }
 
 #pragma unroll 1
     for (int t = t_begin; t <= t_end; ++t) {
@@ -218,19 +231,19 @@ __device__ __forceinline__ void fused_item(const StepArgs& a, const StripItem& i
         for (int k = 0; k < 9; ++k) g[k] = gn_[k];
         // fetch row t + 1 now; it is consumed in the next iteration
         if (t + 1 <= t_last) {
-            const int64_t o = (int64_t)(t + 1) * c.pitch;
+            const uint32_t o = (uint32_t)((t + 1) * c.pitch + ic);
 #pragma unroll
-            for (int k = 0; k < 9; ++k) gn_[k] = in_grid ? S::load(fin, col + k * c.plane + o, k) : T(0);
-            if (in_grid) ln_ = T(lin[lcol + o]);
+            for (int k = 0; k < 9; ++k) gn_[k] = S::load(fin + k * plane, o, k);
+            ln_ = T(lin[o]);
         }
         // f-hat of row t - 4 for stage C (read 4 rows ago, now an L2 hit)
         const int p = t - 4;
         const bool do_c = p >= j0 && p < j1;
         T gc[9];
         if (do_c) {
-            const int64_t o = (int64_t)p * c.pitch;
+            const uint32_t o = (uint32_t)(p * c.pitch + ic);
 #pragma unroll
-            for (int k = 0; k < 9; ++k) gc[k] = in_grid ? S::load(fin, col + k * c.plane + o, k) : T(0);
+            for (int k = 0; k < 9; ++k) gc[k] = S::load(fin + k * plane, o, k);
         }
 
         // ---------------------------------------------------------- A: row t
@@ -238,7 +251,7 @@ __device__ __forceinline__ void fused_item(const StepArgs& a, const StripItem& i
             T P, ux, uy, e[9];
             moments(g, P, ux, uy);
             equilibrium(P, ux, uy, e);
-            const T lam = relaxation_time(g, e, lam_old, c);
+            const T lam = relaxation_time(g, e, lam_old, pl);
             const Collision<T> coll(lam, dt);
 #pragma unroll
             for (int k = 0; k < 9; ++k) gbp[4][k] = coll.a_bar * g[k] + coll.b_bar * e[k];
@@ -250,9 +263,8 @@ __device__ __forceinline__ void fused_item(const StepArgs& a, const StripItem& i
         if (q >= qlo && q <= qhi) {
             T fb[9];
             if (q >= 1 && q <= ny - 2) {
-                const T sx = geo[c.geo_off + q] * inv2dxi;
-                transport_row<T, EDGE>(xs, lane, gbp, gbp[2], adk, pos, edge, q == 1, q == ny - 2, sx, inv2deta, half_dt,
-                                       eps, ome, fb);
+                transport_row<T, EDGE>(xs, lane, gbp, gbp[2], adk, pos, edge, q == 1, q == ny - 2, sx_b * geo[q], sy_b,
+                                       mw, fb);
                 if (walls_b) {
                     publish(wb, i, nx, fb);
                     __syncthreads();
@@ -290,8 +302,8 @@ __device__ __forceinline__ void fused_item(const StepArgs& a, const StripItem& i
 
         // ---------------------------------------------------------- C: row t - 4
         if (do_c) {
-            const int64_t node = (int64_t)p * c.pitch;
-            if (out_col) lout[lcol + node] = (typename S::L)lamr[0];
+            const uint32_t node = (uint32_t)(p * c.pitch + ic);
+            if (out_col) lout[node] = (typename S::L)lamr[0];
             T old[3];
             moments(gc, old[0], old[1], old[2]);
             if (p >= 1 && p <= ny - 2) {
@@ -301,8 +313,7 @@ __device__ __forceinline__ void fused_item(const StepArgs& a, const StripItem& i
                 const Collision<T> coll(lamr[0], dt);
 #pragma unroll
                 for (int k = 0; k < 9; ++k) hp[k] = coll.a_hat * gc[k] + coll.b_hat * e[k];
-                const T sx = geo[c.geo_off + p] * inv2dxi;
-                transport_row<T, EDGE>(xs, lane, fh, hp, adk, pos, edge, p == 1, p == ny - 2, sx, inv2deta, dt, eps, ome, gn);
+                transport_row<T, EDGE>(xs, lane, fh, hp, adk, pos, edge, p == 1, p == ny - 2, sx_c * geo[p], sy_c, mw, gn);
                 if (walls_c) {
                     publish(wc, i, nx, gn);
                     __syncthreads();
@@ -313,8 +324,9 @@ __device__ __forceinline__ void fused_item(const StepArgs& a, const StripItem& i
                     }
                 }
                 if (out_col) {
+                    const uint32_t ns = S::kStochastic ? node_seed(lseed, it.cav, p, i) : 0u;
 #pragma unroll
-                    for (int k = 0; k < 9; ++k) S::store(fout, col + k * c.plane + node, k, gn[k]);
+                    for (int k = 0; k < 9; ++k) store_state<S>(fout + k * plane, node, k, gn[k], ns);
                     if (RES) residual_add(gn, old, acc);
                 }
                 if (p == 1 && j0 == 0) {   // bottom wall row from row 1
@@ -322,8 +334,9 @@ __device__ __forceinline__ void fused_item(const StepArgs& a, const StripItem& i
                     wall_source(wc, i, nx, gn, src);
                     extrapolate(src, T(0), g0);
                     if (out_col) {
+                        const uint32_t ns = S::kStochastic ? node_seed(lseed, it.cav, 0, i) : 0u;
 #pragma unroll
-                        for (int k = 0; k < 9; ++k) S::store(fout, col + k * c.plane, k, g0[k]);
+                        for (int k = 0; k < 9; ++k) store_state<S>(fout + k * plane, (uint32_t)ic, k, g0[k], ns);
                         if (RES) residual_add(g0, mom0, acc);
                     }
                 }
@@ -337,8 +350,9 @@ __device__ __forceinline__ void fused_item(const StepArgs& a, const StripItem& i
                 wall_source(wc, i, nx, own, src);
                 extrapolate(src, ulid, gn);
                 if (out_col) {
+                    const uint32_t ns = S::kStochastic ? node_seed(lseed, it.cav, p, i) : 0u;
 #pragma unroll
-                    for (int k = 0; k < 9; ++k) S::store(fout, col + k * c.plane + node, k, gn[k]);
+                    for (int k = 0; k < 9; ++k) store_state<S>(fout + k * plane, node, k, gn[k], ns);
                     if (RES) residual_add(gn, old, acc);
                 }
             } else {   // p == 0: stored with row 1; keep its old moments
@@ -405,6 +419,7 @@ hipError_t launch_fused_step(int prec, const StepArgs& a, const StripItem* items
     case P_FP32: return fused<P_FP32>(a, items, w0, nw, residual, s);
     case P_FP16DEV: return fused<P_FP16DEV>(a, items, w0, nw, residual, s);
     case P_FP32X: return fused<P_FP32X>(a, items, w0, nw, residual, s);
+    case P_FP32SR: return fused<P_FP32SR>(a, items, w0, nw, residual, s);
     }
     return hipErrorInvalidValue;
 }

@@ -152,15 +152,20 @@ __global__ __launch_bounds__(kNodeBlock) void k_stage_c(StepArgs a, const NodeBl
     static_cast<typename S::L*>(a.l_out)[c.l_off + r.id] = static_cast<const T*>(a.lam_new)[c.l_off + r.id];
     if (is_boundary(r.i, r.j, c.nx, c.ny)) return;
     const T* fh = static_cast<const T*>(a.bar_plus);
-    const T* hp = static_cast<const T*>(a.hat_plus);
+    // f-hat+ is read at its own node only: its slot takes the new f-hat in the
+    // arithmetic type, the source of the wall extrapolation of stage CB
+    T* hp = static_cast<T*>(a.hat_plus);
     auto* out = static_cast<typename S::F*>(a.f_out);
     const T* geo = geo_table<T>(a);
     const T dt = T(c.dt);
-    S::store(out, c.f_off + r.id, 0, hp[c.f_off + r.id]);
+    const uint32_t ns = S::kStochastic ? node_seed(mix32(a.seed_ctr[0] ^ mix32(a.step)), c.index, r.j, r.i) : 0u;
+    store_state<S>(out, c.f_off + r.id, 0, hp[c.f_off + r.id], ns);
 #pragma unroll 1
     for (int k = 1; k < 9; ++k) {
         const int64_t o = c.f_off + k * c.plane;
-        S::store(out, o + r.id, k, hp[o + r.id] - dt * transport(fh + o, c, geo, r.i, r.j, k));
+        const T v = hp[o + r.id] - dt * transport(fh + o, c, geo, r.i, r.j, k);
+        hp[o + r.id] = v;
+        store_state<S>(out, o + r.id, k, v, ns);
     }
 }
 
@@ -174,15 +179,17 @@ __global__ __launch_bounds__(kNodeBlock) void k_stage_cb(StepArgs a, const NodeB
     if (!locate(blocks, b0 + blockIdx.x, a.desc, c, r)) return;
     if (!is_boundary(r.i, r.j, c.nx, c.ny)) return;
     auto* out = static_cast<typename S::F*>(a.f_out);
+    const T* fnew = static_cast<const T*>(a.hat_plus);   // new f-hat of the interior, before rounding to storage
     int ni, nj;
     inward(r.i, r.j, c.nx, c.ny, ni, nj);
     const int64_t nid = (int64_t)nj * c.pitch + ni;
     T xnb[9], x[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) xnb[k] = S::load(out, c.f_off + k * c.plane + nid, k);
+    for (int k = 0; k < 9; ++k) xnb[k] = fnew[c.f_off + k * c.plane + nid];
     extrapolate(xnb, r.j == c.ny - 1 ? T(c.u_lid) : T(0), x);
+    const uint32_t ns = S::kStochastic ? node_seed(mix32(a.seed_ctr[0] ^ mix32(a.step)), c.index, r.j, r.i) : 0u;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) S::store(out, c.f_off + k * c.plane + r.id, k, x[k]);
+    for (int k = 0; k < 9; ++k) store_state<S>(out, c.f_off + k * c.plane + r.id, k, x[k], ns);
 }
 
 // Eq. (2.19) partial sums over one node block, from the moments of f-hat
@@ -252,6 +259,7 @@ hipError_t launch_staged_step(int prec, const StepArgs& a, const NodeBlock* bloc
     case P_FP32: return staged<P_FP32>(a, blocks, b0, nb, residual, s);
     case P_FP16DEV: return staged<P_FP16DEV>(a, blocks, b0, nb, residual, s);
     case P_FP32X: return staged<P_FP32X>(a, blocks, b0, nb, residual, s);
+    case P_FP32SR: return staged<P_FP32SR>(a, blocks, b0, nb, residual, s);
     }
     return hipErrorInvalidValue;
 }

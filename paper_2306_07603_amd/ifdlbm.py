@@ -29,12 +29,12 @@ IFDLBM_EDEVICE = -3
 IFDLBM_EDIVERGED = -4
 IFDLBM_ENOTCONVERGED = -5
 
-IFDLBM_FP64, IFDLBM_FP32, IFDLBM_FP16DEV, IFDLBM_FP32X = 0, 1, 2, 3
+IFDLBM_FP64, IFDLBM_FP32, IFDLBM_FP16DEV, IFDLBM_FP32X, IFDLBM_FP32SR = 0, 1, 2, 3, 4
 IFDLBM_KERNEL_FUSED, IFDLBM_KERNEL_STAGED = 0, 1
 IFDLBM_DT_CONTRAVARIANT, IFDLBM_DT_CARTESIAN = 0, 1
 IFDLBM_STATUS_RUNNING, IFDLBM_STATUS_CONVERGED, IFDLBM_STATUS_DIVERGED, IFDLBM_STATUS_NOT_CONVERGED = 0, 1, 2, 3
 
-PRECISIONS = {"fp64": IFDLBM_FP64, "fp32": IFDLBM_FP32, "fp16dev": IFDLBM_FP16DEV, "fp32x": IFDLBM_FP32X}
+PRECISIONS = {"fp64": IFDLBM_FP64, "fp32": IFDLBM_FP32, "fp16dev": IFDLBM_FP16DEV, "fp32x": IFDLBM_FP32X, "fp32sr": IFDLBM_FP32SR}
 KERNELS = {"fused": IFDLBM_KERNEL_FUSED, "staged": IFDLBM_KERNEL_STAGED}
 
 

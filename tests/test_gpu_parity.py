@@ -145,11 +145,68 @@ def test_graph_equals_eager_bitwise(kernel, precision):
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
-def test_rerun_bitwise(kernel):
+@pytest.mark.parametrize("precision", ["fp32", "fp32sr"])
+def test_rerun_bitwise(kernel, precision):
     specs = [W.CavitySpec(65, 65, 800.0, 0.6, 50.0)]
-    a = M.ifdlbm_get_state(gpu(specs, 50, "fp32", kernel), 0)
-    b = M.ifdlbm_get_state(gpu(specs, 50, "fp32", kernel), 0)
+    a = M.ifdlbm_get_state(gpu(specs, 50, precision, kernel), 0)
+    b = M.ifdlbm_get_state(gpu(specs, 50, precision, kernel), 0)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_fp32sr_graph_replay_equals_eager_calls_bitwise(kernel):
+    """Stochastic rounding draws its random words from a counter bumped once
+    per call (eager) or per replay (graph) and the step index within it: a
+    replay of G steps and an eager call of G steps store the same values."""
+    specs = [W.CavitySpec(33, 33, 100.0, 0.8, 60.0), W.CavitySpec(65, 65, 500.0, 1.3, 50.0)]
+    he = gpu(specs, 0, "fp32sr", kernel, residual_every=5)
+    hg = gpu(specs, 0, "fp32sr", kernel, residual_every=5, graph_steps=10)
+    for _ in range(3):
+        M.ifdlbm_step(he, 10)
+        M.ifdlbm_step(hg, 10)
+    for c in range(2):
+        Fe, Le = M.ifdlbm_get_state(he, c)
+        Fg, Lg = M.ifdlbm_get_state(hg, c)
+        assert np.array_equal(Fe, Fg) and np.array_equal(Le, Lg)
+    re_, rg = M.ifdlbm_get_residuals(he), M.ifdlbm_get_residuals(hg)
+    assert np.array_equal(re_[0], rg[0]) and np.array_equal(re_[1], rg[1])
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_fp32sr_rounding_is_unbiased(kernel):
+    """One step from the same FP32 state: the FP64 path gives the exact update
+    v, the stochastically rounded path stores one of the two FP32 neighbours
+    of v, the upper one with probability (v - lo) / (hi - lo)."""
+    spec = W.CavitySpec(129, 129, 400.0, 0.8, 60.0)
+    h32 = gpu([spec], 200, "fp32", kernel)
+    F, L = M.ifdlbm_get_state(h32, 0)
+    F = F.astype(np.float32).astype(np.float64)
+    L = L.astype(np.float32).astype(np.float64)
+    h64 = gpu([spec], 0, "fp64", kernel)
+    hsr = gpu([spec], 0, "fp32sr", kernel)
+    M.ifdlbm_set_state(h64, 0, F, L)
+    M.ifdlbm_set_state(hsr, 0, F, L)
+    M.ifdlbm_step(h64, 1)
+    M.ifdlbm_step(hsr, 1)
+    v = M.ifdlbm_get_state(h64, 0)[0].ravel()
+    sr = M.ifdlbm_get_state(hsr, 0)[0].ravel()
+    rn = v.astype(np.float32)
+    lo = np.where(rn.astype(np.float64) <= v, rn, np.nextafter(rn, np.float32(-np.inf))).astype(np.float64)
+    hi = np.where(rn.astype(np.float64) >= v, rn, np.nextafter(rn, np.float32(np.inf))).astype(np.float64)
+    inexact = hi > lo
+    # every stored value is one of the two neighbours (exactly representable values stay exact)
+    assert np.mean((sr == lo) | (sr == hi)) >= 1 - 1e-5
+    phi = (v[inexact] - lo[inexact]) / (hi[inexact] - lo[inexact])
+    up = (sr[inexact] == hi[inexact]).astype(np.float64)
+    assert inexact.sum() > 100000
+    for b in range(10):
+        sel = (phi >= b / 10) & (phi < (b + 1) / 10)
+        n = int(sel.sum())
+        p = float(phi[sel].mean())
+        freq = float(up[sel].mean())
+        sigma = np.sqrt(max(p * (1 - p), 1e-4) / n)
+        print("bin %d: n %d  P(up) expected %.4f observed %.4f" % (b, n, p, freq), flush=True)
+        assert abs(freq - p) <= 5 * sigma + 1e-3, b
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
@@ -210,13 +267,14 @@ def test_fields_device():
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
-def test_fp32_against_oracle(kernel):
+@pytest.mark.parametrize("precision", ["fp32", "fp32x", "fp32sr"])
+def test_fp32_against_oracle(kernel, precision):
     spec = W.single_small()
-    h = gpu([spec], 2000, "fp32", kernel)
+    h = gpu([spec], 2000, precision, kernel)
     u, v, p = M.ifdlbm_get_fields(h, 0)
     uo, vo, po, _, _ = O.simulate(oparams(spec), 2000)
     errs = (rel(u, uo), rel(v, vo), rel(p, po))
-    print("fp32 errors u v P", errs, flush=True)
+    print(precision, "errors u v P", errs, flush=True)
     assert errs[0] <= FP32_TOL and errs[1] <= FP32_TOL
 
 
@@ -267,6 +325,44 @@ def test_run_to_steady_and_fp32_steady_error(kernel):
     err = max(rel(u32, u64), rel(v32, v64))
     print("fp32 steady velocity error", err, flush=True)
     assert err <= FP32_TOL
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_fp32sr_steady_velocity(kernel):
+    """Converge FP64 to E <= 1e-10, run FP32 storage with stochastic rounding as
+    many steps: the steady velocity stays within 1e-5 of the FP64 one."""
+    spec = W.CavitySpec(65, 65, 100.0, 0.8, 60.0)
+    h64 = gpu([spec], 0, "fp64", kernel, residual_every=500, graph_steps=1000)
+    rc, steps, ru, rp = M.ifdlbm_run_to_steady(h64, 1e-10, 400000)
+    print("fp64 steady after", steps, ru, rp, flush=True)
+    assert rc == M.IFDLBM_OK and M.ifdlbm_status(h64, 0) == M.IFDLBM_STATUS_CONVERGED
+    hsr = gpu([spec], 0, "fp32sr", kernel, residual_every=500, graph_steps=1000)
+    M.ifdlbm_step(hsr, int(steps[0]))
+    u64, v64, _ = M.ifdlbm_get_fields(h64, 0)
+    u32, v32, _ = M.ifdlbm_get_fields(hsr, 0)
+    err = max(rel(u32, u64), rel(v32, v64))
+    print("fp32sr steady velocity error", err, flush=True)
+    assert err <= FP32_TOL
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_batch_fp32sr_bench_configuration_against_oracle(kernel):
+    """The 256-cavity batch exactly as the benchmark times it (FP32 storage with
+    stochastic rounding, one launch per step, 100-step graph replays, residual
+    sums every 100 steps): after 200 steps, one sampled cavity of every side
+    against the FP64 oracle."""
+    specs = W.batch_sweep()
+    steps = 200
+    h = gpu(specs, steps, "fp32sr", kernel, residual_every=100, graph_steps=100, batched=1)
+    picks = []
+    for side in (65, 129, 257, 513):
+        picks += [i for i, s in enumerate(specs) if s.n_xi == side][:1]
+    for c in picks:
+        u, v, p = M.ifdlbm_get_fields(h, c)
+        uo, vo, po, _, _ = O.simulate(oparams(specs[c]), steps)
+        errs = (rel(u, uo), rel(v, vo), rel(p, po))
+        print(c, specs[c], "fp32sr errors u v P", errs, flush=True)
+        assert errs[0] <= FP32_TOL and errs[1] <= FP32_TOL, c
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
