@@ -95,6 +95,7 @@ typedef struct {
     int32_t batched;        /* 1: all cavities in one launch per step; 0: one launch per cavity       */
     int32_t graph_steps;    /* > 0: replay steps from a captured HIP graph of this many steps         */
     int32_t dt_rule;        /* IFDLBM_DT_CONTRAVARIANT | IFDLBM_DT_CARTESIAN                          */
+    int32_t segment_rows;   /* fused kernel: rows per work item, 0 = automatic, else in [16, 4096]    */
     void*   hip_stream;     /* hipStream_t to enqueue on, or NULL for the null stream                 */
 } ifdlbm_options;
 
@@ -110,12 +111,15 @@ typedef struct {
 } ifdlbm_info_t;
 
 /* Fills *opt with the defaults: FP64, cfl 0.5, mix 0.5, rho0 1, gamma_min 1e-6, residual_every 1,
-   fused kernel, batched, no graph, contravariant time-step rule, null stream. */
+   fused kernel, batched, no graph, contravariant time-step rule, automatic segment rows, null stream. */
 int ifdlbm_default_options(ifdlbm_options* opt);
 
 /* Validates cav[0..n_cav) and *opt, builds the metric terms of Eqs. (3.2)-(3.8.2) in FP64 on the host,
    allocates the device state and applies Step (1): u = 0, P = 0 except u = (u_lid, 0) on the top row
    (corners included), f-hat = f_eq, lambda = U / (Re c_s^2).  *out receives the handle.
+   Size limits: n_xi <= 32767 and n_eta * pitch <= 2^25 nodes per cavity (pitch = n_xi rounded up to a
+   multiple of 16), so that the nine planes of one cavity span less than 4 GiB in FP64 and are addressed with
+   32-bit byte offsets.
    Errors: EINVAL (bad argument, nothing allocated), ENOMEM, EDEVICE. */
 int ifdlbm_create(const ifdlbm_cavity* cav, int32_t n_cav, const ifdlbm_options* opt, ifdlbm_t** out);
 
@@ -175,6 +179,50 @@ int ifdlbm_info(ifdlbm_t* h, ifdlbm_info_t* info);
    J and grad are caller-owned.  Errors: EINVAL, ENOMEM, EDEVICE. */
 int ifdlbm_gradient(const ifdlbm_cavity* cav, const ifdlbm_options* opt, int64_t n_steps, int32_t objective,
                     double* J, double grad[3]);
+
+/* Probe record for the flow-regime study of Section 6.2.  every >= 1: after each step whose count (steps
+   since creation) is a multiple of `every`, append to the record of every cavity the velocity (u, v) at the
+   centre of the cavity (xi = eta = 1/2 of the computational square, the point whose velocity Section 6.2
+   follows; the mean of the two or four nearest nodes when n_xi or n_eta is even) and the kinetic energy of
+   Eq. (5.1).  Each cavity keeps its last `capacity` samples.  Samples are taken on the device, inside graph
+   replays too (graph_steps must then be a multiple of `every`).  every = 0 stops recording and frees the
+   record; every call discards the samples taken so far.  Errors: EINVAL, ENOMEM, EDEVICE. */
+int ifdlbm_record(ifdlbm_t* h, int32_t every, int32_t capacity);
+
+/* Copies the record of cavity cav, oldest first: the newest min(max_samples, samples kept) samples, their
+   count in *n.  steps[i] is the step count after which sample i was taken (time = steps[i] * dt of the
+   cavity).  Caller-owned arrays of max_samples values, any of steps, u, v, ke may be NULL.  Synchronises the
+   handle's stream.  Errors: EINVAL, EDEVICE. */
+int ifdlbm_get_record(ifdlbm_t* h, int32_t cav, int32_t max_samples, int32_t* n, int64_t* steps, double* u,
+                      double* v, double* ke);
+
+/* Time step dt of cavity cav (the rule of options.dt_rule). */
+int ifdlbm_time_step(ifdlbm_t* h, int32_t cav, double* dt);
+
+/* Flow regime of a sampled series (ifdlbm_classify) */
+#define IFDLBM_REGIME_STEADY         0
+#define IFDLBM_REGIME_PERIODIC       1
+#define IFDLBM_REGIME_QUASI_PERIODIC 2
+#define IFDLBM_REGIME_APERIODIC      3
+
+typedef struct {
+    int32_t regime;             /* IFDLBM_REGIME_*                                                       */
+    double  mean;               /* mean of the series                                                    */
+    double  rel_amplitude;      /* (max - min) / 2 / max |x|                                             */
+    double  f_main;             /* principal frequency, cycles per unit time (0 when steady)             */
+    double  f_second;           /* strongest peak away from the multiples of f_main (0 when none)        */
+    double  harmonic_fraction;  /* share of the fluctuation energy at f_main and its multiples           */
+    double  second_fraction;    /* share at f_second                                                     */
+} ifdlbm_regime_t;
+
+/* Host-side classification of n >= 16 samples x (spacing dt_sample in time units), for instance the u or ke
+   of ifdlbm_get_record after the transient.  Steady when rel_amplitude <= steady_tol.  Otherwise, from the
+   power spectrum of the Hann-windowed series (zero-padded FFT): periodic when at least 90% of the
+   fluctuation energy lies within the main lobe of the principal frequency and its multiples; quasi-periodic
+   when a second peak away from those multiples holds at least 2% of the energy and at least half of the
+   rest; aperiodic otherwise.  Frequencies are refined by a parabola through the log-spectrum.  Errors:
+   EINVAL (n < 16 or > 2^22, dt_sample <= 0, steady_tol < 0, non-finite samples). */
+int ifdlbm_classify(const double* x, int64_t n, double dt_sample, double steady_tol, ifdlbm_regime_t* out);
 
 /* Frees the handle and its device memory; NULL-safe. */
 void ifdlbm_destroy(ifdlbm_t* h);

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libifdlbm.so")
-SOURCES = ["api.hip", "kernels_common.hip", "step_staged.hip", "step_fused.hip", "gradient.hip"]
+SOURCES = ["api.hip", "kernels_common.hip", "step_staged.hip", "step_fused.hip", "gradient.hip", "regime.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -31,20 +31,22 @@ def _compile(src: str, obj: str, extra) -> None:
         raise RuntimeError("hipcc failed on %s" % src)
 
 
-def build(extra=(), jobs: int = 4) -> str:
-    objdir = os.path.join(PKG, "_build")
+def build(extra=(), jobs: int = 4, out: str = LIB, objdir: str = "") -> str:
+    """Compile every source with the flags above plus `extra` (e.g. -D tuning
+    knobs of step_fused.hip) and link `out`."""
+    objdir = objdir or os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = [os.path.join(objdir, s.replace(".hip", ".o")) for s in SOURCES]
+    objs = [os.path.join(objdir, os.path.splitext(s)[0] + ".o") for s in SOURCES]
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         list(ex.map(lambda so: _compile(so[0], so[1], list(extra)), zip(SOURCES, objs)))
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tmp = out + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(" ".join(cmd) + "\n" + r.stdout + r.stderr)
         raise RuntimeError("link of libifdlbm.so failed")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -15,15 +15,20 @@
 
 using namespace ifd;
 
-namespace {
+namespace ifd {
 
 thread_local std::string g_last_error;
 
+// Records the text of the last error of this thread and returns code.
 int fail(int code, const std::string& msg)
 {
     g_last_error = msg;
     return code;
 }
+
+}  // namespace ifd
+
+namespace {
 
 #define IFD_HIP(expr)                                                                                   \
     do {                                                                                                \
@@ -34,8 +39,16 @@ int fail(int code, const std::string& msg)
 constexpr double kCs2 = 1.0 / 3.0;
 
 // Rows per segment of the fused kernel's work items (the columns per strip
-// are at most kStripOut).
-constexpr int kSegRows = 64;
+// are at most kStripOut).  Automatic choice: the longest segment (fewest
+// recomputed halo rows) that still gives kTargetItems work items, so that the
+// GPU stays full through the tail of a launch; the shortest otherwise.
+constexpr int kSegCandidates[] = {128, 96, 64, 48, 32, 24, 16};
+constexpr int kMinSegRows = 8;
+constexpr int kTargetItems = 4096;
+constexpr int kXcds = 8;   // MI355X: workgroups are dealt to the 8 XCDs in turn
+#ifndef IFD_ITEM_ORDER
+#define IFD_ITEM_ORDER 1   // 0: longest first over all items; 1: per-XCD queues of whole cavities
+#endif
 
 int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
@@ -75,8 +88,11 @@ struct ifdlbm_s {
     std::vector<NodeBlock> act_blocks;
     NodeBlock* d_act_blocks = nullptr;
     // strip items of the running cavities (fused step)
-    std::vector<StripItem> act_items;
+    std::vector<StripItem> act_items;      // per cavity, contiguous (unit = index)
     StripItem* d_act_items = nullptr;
+    std::vector<StripItem> act_sorted;     // the same items, longest first (batched launch)
+    StripItem* d_act_sorted = nullptr;
+    int seg_rows = 0;
     size_t max_units = 0;
     std::vector<int32_t> unit_first, unit_count;   // per cavity, in the active unit list
     int32_t *d_unit_first = nullptr, *d_unit_count = nullptr;
@@ -85,6 +101,15 @@ struct ifdlbm_s {
     double* d_scratch = nullptr;                    // 10 * max nodes doubles
     uint32_t* d_seed = nullptr;                     // stochastic-rounding step counter
     size_t scratch_elems = 0;
+
+    // probe record (centre velocity and kinetic energy every rec_every steps)
+    int rec_every = 0, rec_capacity = 0;
+    int64_t rec_first_step = 0;                     // step count after which sample 0 is taken
+    double* d_rec = nullptr;                        // [n_cav][capacity][3]
+    uint32_t* d_rec_count = nullptr;
+    double* d_probe_partial = nullptr;              // one double per node block
+    std::vector<int32_t> all_first, all_count;      // node blocks of each cavity in all_blocks
+    int32_t *d_all_first = nullptr, *d_all_count = nullptr;
 
     std::vector<int> status;
     std::vector<double> res_u, res_p;
@@ -98,10 +123,87 @@ namespace {
 int units_per_step(const ifdlbm_s* h) { return h->opt.kernel == IFDLBM_KERNEL_STAGED ? 5 : 1; }
 
 // Rebuild the unit lists of the running cavities (after creation, retirement or restore).
+// First row of segment g of ng over ny rows: the even split, moved to the
+// nearest row that is 4 (mod 5).  The fused kernel's march then starts at a
+// row that is 0 (mod 5), so every row is computed by the same unrolled copy
+// of the row code whatever the segmentation, and results do not depend on
+// the composition of the batch.  Segments of >= 16 rows move by <= 2 rows at
+// each end and keep >= 4 rows.
+int segment_start(int g, int ng, int ny)
+{
+    if (g <= 0) return 0;
+    if (g >= ng) return ny;
+    const int b = (int)((int64_t)g * ny / ng);
+    const int r = ((b - 4) % 5 + 5) % 5;
+    return r <= 2 ? b - r : b + (5 - r);
+}
+
+int segment_rows(const ifdlbm_s* h)
+{
+    if (h->opt.segment_rows > 0) return h->opt.segment_rows;
+    for (int seg : kSegCandidates) {
+        size_t n = 0;
+        for (int c = 0; c < h->n_cav; ++c)
+            if (h->desc[c].active) n += (size_t)ceil_div(h->desc[c].ny, seg) * ceil_div(h->desc[c].nx, kStripOut);
+        if (n >= (size_t)kTargetItems) return seg;
+    }
+    return kSegCandidates[sizeof(kSegCandidates) / sizeof(kSegCandidates[0]) - 1];
+}
+
+// Order of the items in the batched launch.  Workgroup w of a launch goes to
+// XCD w % 8 (each XCD has its own L2), so position 8 r + x is the r-th item of
+// XCD x.  The strips of one row segment of one cavity form a group (they read
+// each other's halo columns); groups are dealt to the XCDs longest first, each
+// to the least loaded XCD (LPT), and every XCD runs its groups longest first,
+// so that neighbouring strips share one L2 and short groups fill the tail.
+// Queues are padded to equal length with empty items.
+int item_cost(const StripItem& it) { return it.j1 - it.j0 + 8; }
+
+void order_for_batch(ifdlbm_s* h)
+{
+    h->act_sorted.clear();
+    if (h->act_items.empty()) return;
+#if IFD_ITEM_ORDER == 0
+    // plain longest-first order over all items
+    h->act_sorted = h->act_items;
+    std::stable_sort(h->act_sorted.begin(), h->act_sorted.end(),
+                     [](const StripItem& x, const StripItem& y) { return item_cost(x) > item_cost(y); });
+#else
+    struct Group {
+        int64_t cost;
+        size_t first, count;
+    };
+    std::vector<Group> groups;
+    for (size_t u = 0; u < h->act_items.size(); ++u) {
+        const StripItem& it = h->act_items[u];
+        if (groups.empty() || h->act_items[groups.back().first].cav != it.cav ||
+            h->act_items[groups.back().first].j0 != it.j0)
+            groups.push_back({0, u, 0});
+        groups.back().cost += item_cost(it);
+        groups.back().count++;
+    }
+    std::stable_sort(groups.begin(), groups.end(), [](const Group& x, const Group& y) { return x.cost > y.cost; });
+    std::vector<std::vector<StripItem>> queue(kXcds);
+    std::vector<int64_t> load(kXcds, 0);
+    for (const Group& g : groups) {
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[x] += g.cost;
+        for (size_t u = g.first; u < g.first + g.count; ++u) queue[x].push_back(h->act_items[u]);
+    }
+    size_t rows = 0;
+    for (const auto& q : queue) rows = std::max(rows, q.size());
+    const StripItem empty{0, 0, 0, 0, 0, -1};
+    for (size_t r = 0; r < rows; ++r)
+        for (int x = 0; x < kXcds; ++x) h->act_sorted.push_back(r < queue[x].size() ? queue[x][r] : empty);
+#endif
+}
+
 int rebuild_worklists(ifdlbm_s* h)
 {
     h->act_blocks.clear();
     h->act_items.clear();
+    const int seg = segment_rows(h);
+    h->seg_rows = seg;
     for (int c = 0; c < h->n_cav; ++c) {
         const bool run = h->desc[c].active != 0;
         if (h->opt.kernel == IFDLBM_KERNEL_STAGED) {
@@ -115,21 +217,26 @@ int rebuild_worklists(ifdlbm_s* h)
             h->unit_first[c] = (int32_t)h->act_items.size();
             if (run) {
                 const CavityDesc& d = h->desc[c];
-                const int ns = ceil_div(d.nx, kStripOut), ng = ceil_div(d.ny, kSegRows);
+                const int ns = ceil_div(d.nx, kStripOut), ng = ceil_div(d.ny, seg);
                 for (int g = 0; g < ng; ++g)
                     for (int s = 0; s < ns; ++s)
                         h->act_items.push_back({c, (int16_t)(s * d.nx / ns), (int16_t)((s + 1) * d.nx / ns),
-                                                g * d.ny / ng, (g + 1) * d.ny / ng});
+                                                segment_start(g, ng, d.ny), segment_start(g + 1, ng, d.ny),
+                                                (int32_t)h->act_items.size()});
             }
             h->unit_count[c] = (int32_t)h->act_items.size() - h->unit_first[c];
         }
     }
+    order_for_batch(h);
     if (!h->act_blocks.empty())
         IFD_HIP(hipMemcpyAsync(h->d_act_blocks, h->act_blocks.data(), h->act_blocks.size() * sizeof(NodeBlock),
                                hipMemcpyHostToDevice, h->stream));
-    if (!h->act_items.empty())
+    if (!h->act_items.empty()) {
         IFD_HIP(hipMemcpyAsync(h->d_act_items, h->act_items.data(), h->act_items.size() * sizeof(StripItem),
                                hipMemcpyHostToDevice, h->stream));
+        IFD_HIP(hipMemcpyAsync(h->d_act_sorted, h->act_sorted.data(), h->act_sorted.size() * sizeof(StripItem),
+                               hipMemcpyHostToDevice, h->stream));
+    }
     IFD_HIP(hipMemcpyAsync(h->d_unit_first, h->unit_first.data(), h->n_cav * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
     IFD_HIP(hipMemcpyAsync(h->d_unit_count, h->unit_count.data(), h->n_cav * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
     IFD_HIP(hipMemcpyAsync(h->d_desc, h->desc.data(), h->n_cav * sizeof(CavityDesc), hipMemcpyHostToDevice, h->stream));
@@ -170,7 +277,7 @@ int enqueue_step(ifdlbm_s* h, bool residual, uint32_t local)
     hipError_t e = hipSuccess;
     if (h->opt.batched) {
         e = staged ? launch_staged_step(prec, a, h->d_act_blocks, 0, (int)h->act_blocks.size(), residual, h->stream)
-                   : launch_fused_step(prec, a, h->d_act_items, 0, (int)h->act_items.size(), residual, h->stream);
+                   : launch_fused_step(prec, a, h->d_act_sorted, 0, (int)h->act_sorted.size(), residual, h->stream);
     } else {
         for (int c = 0; c < h->n_cav && e == hipSuccess; ++c) {
             if (!h->unit_count[c]) continue;
@@ -181,6 +288,16 @@ int enqueue_step(ifdlbm_s* h, bool residual, uint32_t local)
     if (e == hipSuccess && residual)
         e = launch_reduce_partials(h->d_partial, h->d_unit_first, h->d_unit_count, h->n_cav, h->d_res, h->stream);
     if (e != hipSuccess) return fail(IFDLBM_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
+    return IFDLBM_OK;
+}
+
+// Probe record of the current state (after a step).
+int enqueue_probe(ifdlbm_s* h)
+{
+    hipError_t e = launch_probe(h->opt.precision, h->d_f[h->cur], h->d_desc, h->n_cav, h->d_all_blocks,
+                                (int)h->all_blocks.size(), h->d_probe_partial, h->d_all_first, h->d_all_count, h->d_rec,
+                                h->d_rec_count, h->rec_capacity, h->stream);
+    if (e != hipSuccess) return fail(IFDLBM_EDEVICE, std::string("probe launch: ") + hipGetErrorString(e));
     return IFDLBM_OK;
 }
 
@@ -197,6 +314,10 @@ int eager_steps(ifdlbm_s* h, int64_t n)
         if (rc) return rc;
         h->cur ^= 1;
         h->step_count++;
+        if (h->rec_every > 0 && h->step_count % h->rec_every == 0) {
+            rc = enqueue_probe(h);
+            if (rc) return rc;
+        }
     }
     return IFDLBM_OK;
 }
@@ -220,6 +341,8 @@ int build_graph(ifdlbm_s* h)
     for (int s = 0; s < G && rc == IFDLBM_OK; ++s) {
         rc = enqueue_step(h, is_residual_step(h, s), (uint32_t)s);
         h->cur ^= 1;
+        // the graph starts at a multiple of G, and G is a multiple of rec_every
+        if (rc == IFDLBM_OK && h->rec_every > 0 && (s + 1) % h->rec_every == 0) rc = enqueue_probe(h);
     }
     hipError_t e = hipStreamEndCapture(h->stream, &graph);
     h->cur = cur0;
@@ -304,8 +427,9 @@ void free_all(ifdlbm_s* h)
 {
     if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
     void* ptrs[] = {h->d_f[0], h->d_f[1], h->d_l[0], h->d_l[1], h->d_desc, h->d_geo, h->d_geo32, h->d_hp, h->d_bp,
-                    h->d_fb, h->d_ln, h->d_all_blocks, h->d_act_blocks, h->d_act_items, h->d_unit_first,
-                    h->d_unit_count, h->d_partial, h->d_res, h->d_scratch, h->d_seed};
+                    h->d_fb, h->d_ln, h->d_all_blocks, h->d_act_blocks, h->d_act_items, h->d_act_sorted, h->d_unit_first,
+                    h->d_unit_count, h->d_partial, h->d_res, h->d_scratch, h->d_seed, h->d_rec, h->d_rec_count,
+                    h->d_probe_partial, h->d_all_first, h->d_all_count};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
@@ -341,6 +465,7 @@ int ifdlbm_default_options(ifdlbm_options* opt)
     opt->batched = 1;
     opt->graph_steps = 0;
     opt->dt_rule = IFDLBM_DT_CONTRAVARIANT;
+    opt->segment_rows = 0;
     opt->hip_stream = nullptr;
     return IFDLBM_OK;
 }
@@ -359,13 +484,15 @@ int ifdlbm_create(const ifdlbm_cavity* cav, int32_t n_cav, const ifdlbm_options*
     if (o.dt_rule != IFDLBM_DT_CONTRAVARIANT && o.dt_rule != IFDLBM_DT_CARTESIAN) return fail(IFDLBM_EINVAL, "unknown dt_rule");
     if (o.graph_steps < 0 || (o.graph_steps > 0 && (o.graph_steps % 2 != 0 || o.graph_steps % o.residual_every != 0)))
         return fail(IFDLBM_EINVAL, "graph_steps must be 0, or even and a multiple of residual_every");
+    if (o.segment_rows != 0 && (o.segment_rows < 16 || o.segment_rows > 4096))
+        return fail(IFDLBM_EINVAL, "segment_rows must be 0 (automatic) or in [16, 4096]");
     for (int c = 0; c < n_cav; ++c) {
         const ifdlbm_cavity& v = cav[c];
         const std::string id = "cavity " + std::to_string(c) + ": ";
         if (v.n_xi < 5 || v.n_eta < 5) return fail(IFDLBM_EINVAL, id + "n_xi and n_eta must be >= 5");
-        // 32-bit byte offsets inside a plane: n_eta * pitch * 8 < 2^31
-        if (v.n_xi > 32767 || (int64_t)((v.n_xi + 15) / 16 * 16) * v.n_eta > (int64_t)1 << 28)
-            return fail(IFDLBM_EINVAL, id + "grid too large (n_xi <= 32767, n_eta * n_xi <= 2^28)");
+        // 32-bit byte offsets over the nine planes of a cavity: 9 * n_eta * pitch * 8 < 2^32
+        if (v.n_xi > 32767 || (int64_t)((v.n_xi + 15) / 16 * 16) * v.n_eta > (int64_t)1 << 25)
+            return fail(IFDLBM_EINVAL, id + "grid too large (n_xi <= 32767, n_eta * pitch <= 2^25)");
         if (!(v.theta_deg > 0.0 && v.theta_deg <= 90.0)) return fail(IFDLBM_EINVAL, id + "theta_deg must be in (0, 90]");
         if (!(v.n > 0.0) || !std::isfinite(v.n)) return fail(IFDLBM_EINVAL, id + "n must be > 0");
         if (!(v.re > 0.0) || !std::isfinite(v.re)) return fail(IFDLBM_EINVAL, id + "re must be > 0");
@@ -440,8 +567,10 @@ int ifdlbm_create(const ifdlbm_cavity* cav, int32_t n_cav, const ifdlbm_options*
         const int64_t nn = (int64_t)d.nx * d.ny;
         max_nodes = std::max(max_nodes, nn);
         n_blocks += (size_t)((nn + kNodeBlock - 1) / kNodeBlock);
-        n_items += (size_t)ceil_div(d.ny, kSegRows) * ceil_div(d.nx, kStripOut);
+        n_items += (size_t)ceil_div(d.ny, kMinSegRows) * ceil_div(d.nx, kStripOut);
+        h->all_first.push_back((int32_t)h->all_blocks.size());
         for (int n = 0; n < nn; n += kNodeBlock) h->all_blocks.push_back({c, n});
+        h->all_count.push_back((int32_t)h->all_blocks.size() - h->all_first.back());
     }
     h->f_elems = (size_t)f_off;
     h->l_elems = (size_t)l_off;
@@ -466,12 +595,16 @@ int ifdlbm_create(const ifdlbm_cavity* cav, int32_t n_cav, const ifdlbm_options*
     if (!rc) rc = dalloc(&h->d_all_blocks, h->all_blocks.size() * sizeof(NodeBlock));
     if (!rc) rc = dalloc(&h->d_act_blocks, n_blocks * sizeof(NodeBlock));
     if (!rc) rc = dalloc(&h->d_act_items, n_items * sizeof(StripItem));
+    // per-XCD queues are padded to equal length: at most n_items * kXcds entries
+    if (!rc) rc = dalloc(&h->d_act_sorted, n_items * kXcds * sizeof(StripItem));
     if (!rc) rc = dalloc(&h->d_unit_first, n_cav * sizeof(int32_t));
     if (!rc) rc = dalloc(&h->d_unit_count, n_cav * sizeof(int32_t));
     if (!rc) rc = dalloc(&h->d_partial, h->max_units * kPartials * sizeof(double));
     if (!rc) rc = dalloc(&h->d_res, (size_t)n_cav * kPartials * sizeof(double));
     if (!rc) rc = dalloc(&h->d_scratch, h->scratch_elems * sizeof(double));
     if (!rc) rc = dalloc(&h->d_seed, sizeof(uint32_t));
+    if (!rc) rc = dalloc(&h->d_all_first, n_cav * sizeof(int32_t));
+    if (!rc) rc = dalloc(&h->d_all_count, n_cav * sizeof(int32_t));
     if (rc) return bail(rc);
 
     std::vector<float> geo32(geo.begin(), geo.end());
@@ -482,6 +615,8 @@ int ifdlbm_create(const ifdlbm_cavity* cav, int32_t n_cav, const ifdlbm_options*
     if (e == hipSuccess) e = copy(h->d_geo32, geo32.data(), geo32.size() * sizeof(float));
     if (e == hipSuccess) e = copy(h->d_all_blocks, h->all_blocks.data(), h->all_blocks.size() * sizeof(NodeBlock));
     if (e == hipSuccess) e = copy(h->d_desc, h->desc.data(), n_cav * sizeof(CavityDesc));
+    if (e == hipSuccess) e = copy(h->d_all_first, h->all_first.data(), n_cav * sizeof(int32_t));
+    if (e == hipSuccess) e = copy(h->d_all_count, h->all_count.data(), n_cav * sizeof(int32_t));
     if (e == hipSuccess) e = hipMemsetAsync(h->d_res, 0, (size_t)n_cav * kPartials * sizeof(double), h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(h->d_seed, 0, sizeof(uint32_t), h->stream);
     if (e == hipSuccess)
@@ -732,6 +867,76 @@ int ifdlbm_gradient(const ifdlbm_cavity* cav, const ifdlbm_options* opt, int64_t
     if (own) (void)hipStreamDestroy(s);
     if (e != hipSuccess)
         return fail(e == hipErrorOutOfMemory ? IFDLBM_ENOMEM : IFDLBM_EDEVICE, err);
+    return IFDLBM_OK;
+}
+
+int ifdlbm_record(ifdlbm_t* h, int32_t every, int32_t capacity)
+{
+    if (!h) return fail(IFDLBM_EINVAL, "null handle");
+    if (every < 0) return fail(IFDLBM_EINVAL, "every must be >= 0");
+    if (every > 0 && capacity < 1) return fail(IFDLBM_EINVAL, "capacity must be >= 1");
+    if (every > 0 && h->opt.graph_steps > 0 && h->opt.graph_steps % every != 0)
+        return fail(IFDLBM_EINVAL, "graph_steps must be a multiple of the recording interval");
+    if (every > 0 && (int64_t)h->n_cav * capacity * 3 > ((int64_t)1 << 31))
+        return fail(IFDLBM_EINVAL, "record too large (n_cavities * capacity * 3 must fit 2^31 doubles)");
+    IFD_HIP(hipStreamSynchronize(h->stream));
+    void* old[] = {h->d_rec, h->d_rec_count, h->d_probe_partial};
+    for (void* p : old)
+        if (p) IFD_HIP(hipFree(p));
+    h->d_rec = nullptr;
+    h->d_rec_count = nullptr;
+    h->d_probe_partial = nullptr;
+    h->rec_every = 0;
+    h->rec_capacity = 0;
+    h->graph_dirty = true;
+    if (every == 0) return IFDLBM_OK;
+    int rc = dalloc(&h->d_rec, (size_t)h->n_cav * capacity * 3 * sizeof(double));
+    if (!rc) rc = dalloc(&h->d_rec_count, sizeof(uint32_t));
+    if (!rc) rc = dalloc(&h->d_probe_partial, h->all_blocks.size() * sizeof(double));
+    if (rc) return rc;
+    IFD_HIP(hipMemsetAsync(h->d_rec_count, 0, sizeof(uint32_t), h->stream));
+    IFD_HIP(hipStreamSynchronize(h->stream));
+    h->rec_every = every;
+    h->rec_capacity = capacity;
+    h->rec_first_step = (h->step_count / every + 1) * every;
+    return IFDLBM_OK;
+}
+
+int ifdlbm_get_record(ifdlbm_t* h, int32_t cav, int32_t max_samples, int32_t* n, int64_t* steps, double* u, double* v,
+                      double* ke)
+{
+    int rc = check_cav(h, cav);
+    if (rc) return rc;
+    if (!n) return fail(IFDLBM_EINVAL, "null sample count pointer");
+    if (max_samples < 0) return fail(IFDLBM_EINVAL, "max_samples must be >= 0");
+    *n = 0;
+    if (h->rec_every == 0) return IFDLBM_OK;
+    uint32_t count = 0;
+    IFD_HIP(hipMemcpyAsync(&count, h->d_rec_count, sizeof(uint32_t), hipMemcpyDeviceToHost, h->stream));
+    std::vector<double> r((size_t)h->rec_capacity * 3);
+    IFD_HIP(hipMemcpyAsync(r.data(), h->d_rec + (size_t)cav * h->rec_capacity * 3, r.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, h->stream));
+    IFD_HIP(hipStreamSynchronize(h->stream));
+    const int64_t avail = std::min<int64_t>(count, h->rec_capacity);
+    const int64_t m = std::min<int64_t>(avail, max_samples);
+    for (int64_t q = 0; q < m; ++q) {
+        const int64_t sample = (int64_t)count - m + q;
+        const size_t slot = (size_t)(sample % h->rec_capacity);
+        if (steps) steps[q] = h->rec_first_step + sample * h->rec_every;
+        if (u) u[q] = r[slot * 3 + 0];
+        if (v) v[q] = r[slot * 3 + 1];
+        if (ke) ke[q] = r[slot * 3 + 2];
+    }
+    *n = (int32_t)m;
+    return IFDLBM_OK;
+}
+
+int ifdlbm_time_step(ifdlbm_t* h, int32_t cav, double* dt)
+{
+    int rc = check_cav(h, cav);
+    if (rc) return rc;
+    if (!dt) return fail(IFDLBM_EINVAL, "null dt pointer");
+    *dt = h->desc[cav].dt;
     return IFDLBM_OK;
 }
 

@@ -31,6 +31,7 @@ struct StripItem {
     int32_t cav;
     int16_t i0, i1;
     int32_t j0, j1;
+    int32_t unit;   // slot of its residual partial sums (items of a cavity are consecutive slots)
 };
 
 // Residual partial sums of Eq. (2.19) per work unit: sum |u_new - u_old|^2,
@@ -92,6 +93,13 @@ hipError_t launch_state_in(int prec, void* f, void* l, const CavityDesc& hd, dou
 // Kinetic energy of Eq. (5.1) summed per block, reduced on the host in order.
 hipError_t launch_energy(int prec, const void* f, const CavityDesc* desc, const double* geo, int cav_index,
                          const CavityDesc& hd, double* partial, hipStream_t s);
+
+// Probe record of every cavity (centre velocity and kinetic energy of Eq. 5.1)
+// into slot *rec_count % capacity, then *rec_count + 1; blocks [0, nb) are all
+// node blocks, first/count their range per cavity, partial nb doubles.
+hipError_t launch_probe(int prec, const void* f, const CavityDesc* desc, int n_cav, const NodeBlock* blocks, int nb,
+                        double* partial, const int32_t* first, const int32_t* count, double* rec, uint32_t* rec_count,
+                        int capacity, hipStream_t s);
 
 // Tangent-linear kinetic energy of one cavity after n_steps (see ifdlbm_gradient).
 hipError_t tangent_kinetic_energy(int nx, int ny, double re, double n, double theta_deg, double u_lid, double cfl,

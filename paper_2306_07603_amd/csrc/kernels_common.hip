@@ -134,6 +134,82 @@ __global__ __launch_bounds__(256) void k_energy(const void* fv, CavityDesc c, do
     if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
 }
 
+// Probe record, part 1: Eq. (5.1) partial sums per node block of every cavity.
+template <int PREC>
+__global__ __launch_bounds__(256) void k_probe_energy(const void* fv, const CavityDesc* desc, const NodeBlock* blocks,
+                                                      double* partial)
+{
+    using S = Storage<PREC>;
+    using T = typename S::T;
+    __shared__ double sh[256];
+    const NodeBlock nb = blocks[blockIdx.x];
+    const CavityDesc c = desc[nb.cav];
+    const int n = nb.first + (int)threadIdx.x;
+    double e = 0.0;
+    if (n < c.nx * c.ny) {
+        const int j = n / c.nx, i = n - j * c.nx;
+        const int64_t id = (int64_t)j * c.pitch + i;
+        const auto* f = static_cast<const typename S::F*>(fv);
+        T g[9], P, ux, uy;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) g[k] = S::load(f, c.f_off + k * c.plane + id, k);
+        moments(g, P, ux, uy);
+        const double wi = (i == 0 || i == c.nx - 1) ? 0.5 : 1.0;
+        const double wj = (j == 0 || j == c.ny - 1) ? 0.5 : 1.0;
+        const double J = 1.0 + 2.0 * c.cot * (j * c.deta);
+        e = 0.5 * wi * wj * J * c.dxi * c.deta * ((double)ux * ux + (double)uy * uy);
+    }
+    sh[threadIdx.x] = e;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+// Probe record, part 2 (one workgroup): per cavity the kinetic energy (block
+// partials summed in order) and the velocity at the centre of the
+// computational square (xi = eta = 1/2: one node, or the mean of the two or
+// four nearest nodes for an even count) into slot count % capacity of its
+// record, then count + 1.
+template <int PREC>
+__global__ __launch_bounds__(256) void k_probe_finish(const void* fv, const CavityDesc* desc, int n_cav,
+                                                      const double* partial, const int32_t* first,
+                                                      const int32_t* count, double* rec, uint32_t* rec_count,
+                                                      int capacity)
+{
+    using S = Storage<PREC>;
+    using T = typename S::T;
+    const uint32_t nrec = rec_count[0];
+    const int slot = (int)(nrec % (uint32_t)capacity);
+    const auto* f = static_cast<const typename S::F*>(fv);
+    for (int cav = threadIdx.x; cav < n_cav; cav += blockDim.x) {
+        const CavityDesc c = desc[cav];
+        double ke = 0.0;
+        for (int b = first[cav]; b < first[cav] + count[cav]; ++b) ke += partial[b];
+        const int ia = (c.nx - 1) / 2, ib = c.nx / 2, ja = (c.ny - 1) / 2, jb = c.ny / 2;
+        double su = 0.0, sv = 0.0;
+        for (int j = ja; j <= jb; ++j)
+            for (int i = ia; i <= ib; ++i) {
+                const int64_t id = (int64_t)j * c.pitch + i;
+                T g[9], P, ux, uy;
+#pragma unroll
+                for (int k = 0; k < 9; ++k) g[k] = S::load(f, c.f_off + k * c.plane + id, k);
+                moments(g, P, ux, uy);
+                su += (double)ux;
+                sv += (double)uy;
+            }
+        const double inv = 1.0 / ((jb - ja + 1) * (ib - ia + 1));
+        double* r = rec + ((int64_t)cav * capacity + slot) * 3;
+        r[0] = su * inv;
+        r[1] = sv * inv;
+        r[2] = ke;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) rec_count[0] = nrec + 1u;
+}
+
 __global__ void k_seed_bump(uint32_t* ctr) { ctr[0] += 1u; }
 
 inline unsigned blocks_of(const CavityDesc& c) { return (unsigned)((c.nx * c.ny + 255) / 256); }
@@ -216,6 +292,27 @@ hipError_t launch_state_in(int prec, void* f, void* l, const CavityDesc& hd, dou
     case P_FP32SR: hipLaunchKernelGGL(k_state_in<P_FP32SR>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_probe(int prec, const void* f, const CavityDesc* desc, int n_cav, const NodeBlock* blocks, int nb,
+                        double* partial, const int32_t* first, const int32_t* count, double* rec, uint32_t* rec_count,
+                        int capacity, hipStream_t s)
+{
+    if (nb <= 0 || n_cav <= 0) return hipSuccess;
+#define IFD_PROBE(P)                                                                                            \
+    hipLaunchKernelGGL(k_probe_energy<P>, dim3(nb), dim3(256), 0, s, f, desc, blocks, partial);                \
+    hipLaunchKernelGGL(k_probe_finish<P>, dim3(1), dim3(256), 0, s, f, desc, n_cav, partial, first, count, rec, \
+                       rec_count, capacity);
+    switch (prec) {
+    case P_FP64: IFD_PROBE(P_FP64) break;
+    case P_FP32: IFD_PROBE(P_FP32) break;
+    case P_FP16DEV: IFD_PROBE(P_FP16DEV) break;
+    case P_FP32X: IFD_PROBE(P_FP32X) break;
+    case P_FP32SR: IFD_PROBE(P_FP32SR) break;
+    default: return hipErrorInvalidValue;
+    }
+#undef IFD_PROBE
     return hipGetLastError();
 }
 

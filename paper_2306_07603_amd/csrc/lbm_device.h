@@ -30,23 +30,41 @@ __host__ __device__ inline uint32_t mix32(uint32_t x)
     return x;
 }
 
-// Random word of (step, cavity, node); population k takes mix32(seed + k * golden).
-__device__ inline uint32_t node_seed(uint32_t step, int cav, int j, int i)
-{
-    return mix32(step ^ mix32((uint32_t)cav * 0x9E3779B9u ^ mix32((uint32_t)j * 0x85EBCA6Bu ^ (uint32_t)i)));
-}
+// Random words of one node at one step, a function of (step key, cavity,
+// node index) only, so that every kernel and every work decomposition draws
+// the same bits: h = mix32(step_key ^ cav_key ^ node), then four xorshift32
+// steps (Marsaglia's 13/17/5 triple) give five words; population k uses the
+// 16 bits r16(k) of word k / 2.
+__host__ __device__ inline uint32_t cavity_key(int cav) { return mix32((uint32_t)cav * 0x9E3779B9u + 0x632BE5ABu); }
+__host__ __device__ inline uint32_t step_key(uint32_t counter, uint32_t step) { return mix32(counter ^ mix32(step + 0x85EBCA6Bu)); }
 
-__device__ inline uint32_t pop_bits(uint32_t seed, int k) { return mix32(seed + (uint32_t)k * 0x9E3779B9u); }
+struct NodeWords {
+    uint32_t w[5];
+    __device__ __forceinline__ NodeWords(uint32_t skey, uint32_t ckey, uint32_t node)
+    {
+        uint32_t x = mix32(skey ^ ckey ^ node);
+        x = x ? x : 0x6D2B79F5u;   // xorshift32 has no zero state
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+            w[m] = x;
+            x ^= x << 13;
+            x ^= x >> 17;
+            x ^= x << 5;
+        }
+    }
+    __device__ __forceinline__ uint32_t r16(int k) const { return k & 1 ? w[k >> 1] >> 16 : w[k >> 1] & 0xFFFFu; }
+};
 
-// Stochastic rounding of an FP64 value to FP32: add 29 random bits below the
-// FP32 mantissa of the FP64 significand and truncate.  The result is the FP32
-// neighbour above (in magnitude) with probability equal to the discarded
-// fraction, so the rounding error has zero mean; the truncated value converts
-// to FP32 exactly (normal range).
-__device__ inline float round_stochastic(double v, uint32_t r)
+// Stochastic rounding of an FP64 value to FP32: add 16 random bits at the top
+// of the 29 significand bits that FP32 drops, then truncate them.  The result
+// is the FP32 neighbour above (in magnitude) with probability equal to the
+// dropped fraction rounded down to a multiple of 2^-16, so the rounding error
+// has zero mean up to 2^-16 ulp; the truncated value converts to FP32 exactly
+// (normal range).
+__device__ __forceinline__ float round_stochastic(double v, uint32_t r16)
 {
     unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    b += (unsigned long long)(r & 0x1FFFFFFFu);
+    b += (unsigned long long)r16 << 13;
     b &= ~0x1FFFFFFFull;
     return (float)__longlong_as_double((long long)b);
 }
@@ -76,16 +94,24 @@ struct CavityDesc {
 };
 
 // ---------------------------------------------------------------- storage
+// F: stored distribution element; L: stored lambda; T: arithmetic of the
+// distributions; V: arithmetic of Step (2) and of the relaxation coefficients
+// (a function of the state, not a stored increment, so FP32 there perturbs the
+// viscosity by O(1e-7) relative and shifts no fixed point).  cvt / enc convert
+// between F and T (enc rounds to nearest).
 
 template <int PREC> struct Storage;
 
 template <> struct Storage<P_FP64> {
     static constexpr bool kStochastic = false;
-    using F = double;   // distribution element
-    using L = double;   // lambda element
-    using T = double;   // arithmetic
-    __device__ static inline T load(const F* p, int64_t i, int) { return p[i]; }
-    __device__ static inline void store(F* p, int64_t i, int, T v) { p[i] = v; }
+    using F = double;
+    using L = double;
+    using T = double;
+    using V = double;
+    __device__ static inline T cvt(F v, int) { return v; }
+    __device__ static inline F enc(T v, int) { return v; }
+    __device__ static inline T load(const F* p, int64_t i, int k) { return cvt(p[i], k); }
+    __device__ static inline void store(F* p, int64_t i, int k, T v) { p[i] = enc(v, k); }
 };
 
 template <> struct Storage<P_FP32> {
@@ -93,8 +119,11 @@ template <> struct Storage<P_FP32> {
     using F = float;
     using L = float;
     using T = float;
-    __device__ static inline T load(const F* p, int64_t i, int) { return p[i]; }
-    __device__ static inline void store(F* p, int64_t i, int, T v) { p[i] = v; }
+    using V = float;
+    __device__ static inline T cvt(F v, int) { return v; }
+    __device__ static inline F enc(T v, int) { return v; }
+    __device__ static inline T load(const F* p, int64_t i, int k) { return cvt(p[i], k); }
+    __device__ static inline void store(F* p, int64_t i, int k, T v) { p[i] = enc(v, k); }
 };
 
 // FP32 storage with FP64 arithmetic: only the stored state is rounded to FP32.
@@ -103,31 +132,38 @@ template <> struct Storage<P_FP32X> {
     using F = float;
     using L = float;
     using T = double;
-    __device__ static inline T load(const F* p, int64_t i, int) { return (T)p[i]; }
-    __device__ static inline void store(F* p, int64_t i, int, T v) { p[i] = (F)v; }
+    using V = double;
+    __device__ static inline T cvt(F v, int) { return (T)v; }
+    __device__ static inline F enc(T v, int) { return (F)v; }
+    __device__ static inline T load(const F* p, int64_t i, int k) { return cvt(p[i], k); }
+    __device__ static inline void store(F* p, int64_t i, int k, T v) { p[i] = enc(v, k); }
 };
 
-// FP32 storage, FP64 arithmetic, distributions stored with stochastic
-// rounding: at a steady state the rounding of the stored state no longer acts
-// as a constant forcing (with round-to-nearest it shifts the fixed point).
+// FP32 storage, FP64 arithmetic of the distributions, distributions stored
+// with stochastic rounding: at a steady state the rounding of the stored
+// state no longer acts as a constant forcing (with round-to-nearest it
+// shifts, and can freeze, the fixed point).
 template <> struct Storage<P_FP32SR> {
     static constexpr bool kStochastic = true;
     using F = float;
     using L = float;
     using T = double;
-    __device__ static inline T load(const F* p, int64_t i, int) { return (T)p[i]; }
-    __device__ static inline void store(F* p, int64_t i, int, T v) { p[i] = (F)v; }
-    __device__ static inline void store_sr(F* p, int64_t i, T v, uint32_t r) { p[i] = round_stochastic(v, r); }
+    using V = float;
+    __device__ static inline T cvt(F v, int) { return (T)v; }
+    __device__ static inline F enc(T v, int) { return (F)v; }
+    __device__ static inline F enc_sr(T v, uint32_t r16) { return round_stochastic(v, r16); }
+    __device__ static inline T load(const F* p, int64_t i, int k) { return cvt(p[i], k); }
+    __device__ static inline void store(F* p, int64_t i, int k, T v) { p[i] = enc(v, k); }
 };
 
-// Store of a state population: stochastic rounding where the storage asks for it.
+// Encoding of a new state population: stochastic rounding where the storage asks for it.
 template <typename S>
-__device__ __forceinline__ void store_state(typename S::F* p, int64_t i, int k, typename S::T v, uint32_t seed)
+__device__ __forceinline__ typename S::F encode_state(typename S::T v, int k, const NodeWords* nw)
 {
     if constexpr (S::kStochastic)
-        S::store_sr(p, i, v, pop_bits(seed, k));
+        return S::enc_sr(v, nw->r16(k));
     else
-        S::store(p, i, k, v);
+        return S::enc(v, k);
 }
 
 // FP16 storage of g_k / omega_k: the division by the lattice weight puts all
@@ -137,10 +173,13 @@ template <> struct Storage<P_FP16DEV> {
     using F = __half;
     using L = float;
     using T = float;
+    using V = float;
     __device__ static inline float w(int k) { return k == 0 ? 4.0f / 9.0f : (k < 5 ? 1.0f / 9.0f : 1.0f / 36.0f); }
     __device__ static inline float inv_w(int k) { return k == 0 ? 2.25f : (k < 5 ? 9.0f : 36.0f); }
-    __device__ static inline T load(const F* p, int64_t i, int k) { return w(k) * __half2float(p[i]); }
-    __device__ static inline void store(F* p, int64_t i, int k, T v) { p[i] = __float2half_rn(v * inv_w(k)); }
+    __device__ static inline T cvt(F v, int k) { return w(k) * __half2float(v); }
+    __device__ static inline F enc(T v, int k) { return __float2half_rn(v * inv_w(k)); }
+    __device__ static inline T load(const F* p, int64_t i, int k) { return cvt(p[i], k); }
+    __device__ static inline void store(F* p, int64_t i, int k, T v) { p[i] = enc(v, k); }
 };
 
 // ----------------------------------------------------------------- lattice
@@ -239,6 +278,44 @@ template <typename T>
 __device__ __forceinline__ T relaxation_time(const T g[9], const T e[9], T lam_old, const CavityDesc& c)
 {
     return relaxation_time(g, e, lam_old, PowerLaw<T>(c));
+}
+
+// Step (2) in the arithmetic V from d_k = e_k - g_k (T): Pi = -sum c c d, and
+// only its quadratic form enters gamma^2, so the sign drops out.
+template <typename T, typename V>
+__device__ __forceinline__ V relaxation_time_d(const T d[9], V lam_old, const PowerLaw<V>& pl)
+{
+    if (pl.newtonian) return pl.lam_newton;
+    const T s58 = (d[5] + d[6]) + (d[7] + d[8]);
+    const V pxx = V((d[1] + d[3]) + s58);
+    const V pyy = V((d[2] + d[4]) + s58);
+    const V pxy = V((d[5] - d[6]) + (d[7] - d[8]));
+    const V r = recip(V(2) * lam_old + pl.dt);
+    V gamma2 = V(18) * (pxx * pxx + V(2) * pxy * pxy + pyy * pyy) * r * r;
+    gamma2 = gamma2 > pl.g2min ? gamma2 : pl.g2min;
+    return pl.K3 * pow_pos<V>(gamma2, pl.expo);
+}
+
+// Eqs. (2.15)-(2.16) written as x + b (e - x): f-hat+ = g + b_hat (e - g),
+// b_hat = 2 dt / (2 lam + dt); f-bar+ = g + b_bar (e - g), b_bar = 3 dt / (4 lam
+// + 2 dt).  Rounding of b perturbs the relaxation rate only: mass and
+// momentum stay exactly those of g.
+template <typename V>
+struct Relax {
+    V b_hat, b_bar;
+    __device__ __forceinline__ Relax(V lam, V dt)
+    {
+        const V r = recip(V(2) * lam + dt);
+        b_hat = V(2) * dt * r;
+        b_bar = V(1.5) * dt * r;
+    }
+};
+
+// Eq. (2.17) as f = f-bar + b (e - f-bar), b = dt / (4 lam + dt).
+template <typename V>
+__device__ __forceinline__ V half_coef(V lam, V dt)
+{
+    return dt * recip(V(4) * lam + dt);
 }
 
 // Steps (3)-(4): Eq. (2.15) f-hat+ = ((2 lam - dt) g + 2 dt e) / (2 lam + dt) and

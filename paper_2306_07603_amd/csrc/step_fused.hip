@@ -5,38 +5,113 @@
 // Work item: output columns [i0, i1) and rows [j0, j1) of one cavity.  The 64
 // lanes of the wavefront hold columns i0 - 4 .. i0 + 59, one column per lane,
 // and march up the rows.  At row t of the march:
-//   A  (row t)     f-hat and lambda (prefetched one row ahead): moments,
-//                  lambda (Step 2), f-bar+ (Eq. 2.16)
+//   A  (row t)     f-hat and lambda (fetched one row ahead): moments, lambda
+//                  (Step 2, stored), f-bar+ (Eq. 2.16) into a register ring
+//                  and f-hat+ (Eq. 2.15) into a lane-private LDS ring
 //   B  (row t - 2) f-bar(t + dt/2) by Eq. (3.7), walls by extrapolation, and
-//                  f(t + dt/2) by Eq. (2.17)
-//   C  (row t - 4) f-hat+ (Eq. 2.15) recomputed from f-hat of row t - 4
-//                  (read again; it is still in L2), f-hat(t + dt) by
-//                  Eq. (3.6), walls by extrapolation (Step 6), store, residual
+//                  f(t + dt/2) by Eq. (2.17) into a second register ring
+//   C  (row t - 4) f-hat(t + dt) by Eq. (3.6) from the f-hat+ of the LDS
+//                  ring, walls by extrapolation (Step 6), store, residual
 //                  partial sums of Eq. (2.19)
-// The eta-direction stencils read five-row register rings of f-bar+ and
-// f(t + dt/2); the xi-direction stencils read neighbour lanes through one LDS
-// row per population.  The halo costs 8 of 64 lanes across xi and 8 + 4
-// recomputed rows per segment along eta.  The bottom wall row is produced with
-// row 1 (its extrapolation source), the lid row from the row below it.
+// The eta-direction stencils read the register rings (five rows each); the
+// xi-direction stencils read neighbour lanes through one LDS row per
+// population, at per-lane addresses that already point at the upwind side
+// (the sign of the contravariant velocity of Eq. (3.2) is fixed per column
+// and population), so no operand is selected after the read.  The rows of
+// the march are unrolled five times so that ring slots are renamed, not
+// moved.  The halo costs 8 of 64 lanes across xi and 8 + 4 recomputed rows
+// per segment along eta.  The bottom wall row is produced with row 1 (its
+// extrapolation source), the lid row of f-hat(t + dt) with row ny - 2, the
+// lid row of f(t + dt/2) from row ny - 2 kept for one row in the LDS ring.
+//
+// Global memory is addressed through raw buffer resources: one 4-dword
+// resource per array and cavity, the plane of population k as a scalar
+// offset, the row and column as one 32-bit vector offset.
 #include "ifdlbm_internal.h"
 
 namespace ifd {
 namespace {
 
-constexpr int kPad = 2;
-constexpr int kXcds = 8;   // MI355X: workgroups are dealt to the 8 XCDs in turn
+constexpr int kPad = 2;                          // LDS columns beyond the wave on each side
+constexpr int kRowLds = kWaveLanes + 2 * kPad;   // elements of one LDS exchange row
+constexpr int kRing = 5;                         // ring slots: rows t - 4 .. t
+
+// Rows per loop trip (1: rings moved by one slot per row; kRing: renamed) and
+// the smallest number of waves per SIMD the register allocation must allow:
+// FP32 arithmetic, FP64 storage and arithmetic, FP32 storage with FP64
+// arithmetic.  Build-time knobs for tuning.
+#ifndef IFD_FUSED_UNROLL_F32
+#define IFD_FUSED_UNROLL_F32 5
+#endif
+#ifndef IFD_FUSED_UNROLL_F64
+#define IFD_FUSED_UNROLL_F64 1
+#endif
+#ifndef IFD_FUSED_UNROLL_MIXED
+#define IFD_FUSED_UNROLL_MIXED 5
+#endif
+#ifndef IFD_FUSED_ONE_PATH
+#define IFD_FUSED_ONE_PATH 0   // 1: every wave takes the wall-aware code (half the code, a select per point)
+#endif
+#ifndef IFD_FUSED_WAVES_F32
+#define IFD_FUSED_WAVES_F32 2
+#endif
+#ifndef IFD_FUSED_WAVES_F64
+#define IFD_FUSED_WAVES_F64 1
+#endif
+template <int PREC>
+struct Tuning {
+    static constexpr bool kWide = sizeof(typename Storage<PREC>::T) == 8;
+    static constexpr bool kMixed = kWide && sizeof(typename Storage<PREC>::F) == 4;
+    static constexpr int kUnroll = kMixed ? IFD_FUSED_UNROLL_MIXED : (kWide ? IFD_FUSED_UNROLL_F64 : IFD_FUSED_UNROLL_F32);
+    static constexpr int kWaves = kWide ? IFD_FUSED_WAVES_F64 : IFD_FUSED_WAVES_F32;
+    static_assert(kUnroll == 1 || kUnroll == kRing, "the ring is renamed only over a full turn");
+};
+
+// Dword 3 of a raw buffer resource on the gfx9 family (CDNA): 32-bit data
+// format, no swizzle, no index stride.
+constexpr int kRawBufferWord3 = 0x00020000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, kRawBufferWord3);
+}
+
+template <typename F> struct Buf;
+template <> struct Buf<double> {
+    __device__ static double ld(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
+    {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+    }
+    __device__ static void st(double v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
+    {
+        using W = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0u, 0));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(W, v), r, vo, so, 0);
+    }
+};
+template <> struct Buf<float> {
+    __device__ static float ld(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
+    {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+    }
+    __device__ static void st(float v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, vo, so, 0);
+    }
+};
+template <> struct Buf<__half> {
+    __device__ static __half ld(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
+    {
+        return __builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, vo, so, 0));
+    }
+    __device__ static void st(__half v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
+    {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, vo, so, 0);
+    }
+};
 
 template <typename T> __device__ __forceinline__ const T* geo_of(const StepArgs& a);
 template <> __device__ __forceinline__ const double* geo_of<double>(const StepArgs& a) { return a.geo; }
 template <> __device__ __forceinline__ const float* geo_of<float>(const StepArgs& a) { return a.geo32; }
-
-// Work item of block b among nw: consecutive items (neighbouring strips and
-// segments, which share halo rows and columns) go to the same XCD and L2.
-__device__ __forceinline__ int xcd_order(int b, int nw)
-{
-    const int q = nw / kXcds, r = nw % kXcds, x = b % kXcds;
-    return x * q + min(x, r) + b / kXcds;
-}
 
 // Weights of Eq. (2.5) times sign(c) * 2h on the upwind-sorted points a2
 // (two behind), a1 (one behind), c0 and f1 (one ahead):
@@ -46,55 +121,75 @@ __device__ __forceinline__ int xcd_order(int b, int nw)
 template <typename T>
 struct MixedWeights {
     T wf, wa1, wc, wa2;
-    __device__ __forceinline__ explicit MixedWeights(T eps)
-        : wf(eps), wa1(-(T(4) - T(3) * eps)), wc(T(3) * (T(1) - eps)), wa2(T(1) - eps)
+    __device__ __forceinline__ MixedWeights(T eps, T scale)
+        : wf(scale * eps), wa1(-scale * (T(4) - T(3) * eps)), wc(scale * T(3) * (T(1) - eps)),
+          wa2(scale * (T(1) - eps))
     {
     }
     __device__ __forceinline__ T apply(T a2, T a1, T c0, T f1) const { return ((wc * c0 + wa1 * a1) + wa2 * a2) + wf * f1; }
 };
 
-// c_k . grad Phi_k of Eq. (3.4) for the eight moving populations of one row,
-// times the step, subtracted from `base`:
-//   out[k] = base[k] - sx * |dk[k]| * D_xi - sy * D_eta
-// where sx = step a_j / (2 dxi) and sy = step / (2 deta) and D are the signed
-// mixed differences; the xi neighbours come from the LDS row, the eta
-// neighbours from ring slots 0..4 (rows r-2..r+2).  Where the second upwind
-// point would leave the grid (EDGE waves) it is replaced by the linear
-// extrapolation 2 a1 - c0, which gives the first-order difference.
+// Population k of the eta direction moves up (c_ky > 0: 2, 5, 6), down
+// (c_ky < 0: 4, 7, 8) or not at all (0, 1, 3).
+constexpr bool moves_up(int k) { return cyk(k) > 0; }
+constexpr bool moves_down(int k) { return cyk(k) < 0; }
+
+// The xi-stencil view of one lane, fixed for the work item.  The
+// contravariant xi-velocity is a_j d_k(i) with d_k = c_kx - c_ky s_i
+// (Eqs. 3.2-3.8.2): d = 1 for k = 1, -1 for k = 3, and for the pairs
+// (2, 4), (5, 7), (6, 8) the second member has minus the first's d.  The
+// upwind side follows sign(d) (ties: the c >= 0 side; there |d| = 0 and the
+// term vanishes).  Byte offsets into an LDS row: a1/a2/f1 of the first
+// member of each pair, a2m the far point of the mirrored member (whose a1
+// and f1 are the pair's f1 and a1).
 template <typename T, bool EDGE>
-__device__ __forceinline__ void transport_row(T (*xs)[kWaveLanes + 2 * kPad], int lane, const T (&ring)[5][9],
-                                              const T (&base)[9], const T (&adk)[9], const bool (&pos)[9],
-                                              const bool (&edge)[9], bool lo_eta, bool hi_eta, T sx, T sy,
-                                              const MixedWeights<T>& w, T (&out)[9])
-{
+struct XiLane {
+    uint32_t own;           // this lane's column
+    uint32_t a1[3], a2[3], f1[3], a2m[3];
+    T ad[3];                // |d| of the pairs
+    bool edge1, edge3;      // EDGE: second upwind point outside the grid (first-order point, Eq. 2.7 at walls)
+    bool edge_p[3], edge_m[3];
+
+    __device__ __forceinline__ XiLane(int lane, int i, int nx, T s)
+    {
+        constexpr uint32_t E = sizeof(T);
+        own = (uint32_t)(lane + kPad) * E;
+        const T d[3] = {-s, T(1) - s, T(-1) - s};   // d of k = 2, 5, 6
 #pragma unroll
-    for (int k = 1; k < 9; ++k) xs[k - 1][lane + kPad] = ring[2][k];
-    __syncthreads();
-    out[0] = base[0];
-#pragma unroll
-    for (int k = 1; k < 9; ++k) {
-        const T* row = xs[k - 1];
-        const T c0 = ring[2][k];
-        const T m2 = row[lane + kPad - 2], m1 = row[lane + kPad - 1];
-        const T p1 = row[lane + kPad + 1], p2 = row[lane + kPad + 2];
-        const T a1 = pos[k] ? m1 : p1;
-        T a2 = pos[k] ? m2 : p2;
-        const T f1 = pos[k] ? p1 : m1;
-        if (EDGE) a2 = edge[k] ? T(2) * a1 - c0 : a2;
-        T o = base[k] - (sx * adk[k]) * w.apply(a2, a1, c0, f1);
-        if (cyk(k) != 0) {
-            // sign of c_k,eta = c_ky is fixed by k
-            const bool up = cyk(k) > 0;
-            const T e1 = up ? ring[1][k] : ring[3][k];
-            T e2 = up ? ring[0][k] : ring[4][k];
-            const T g1 = up ? ring[3][k] : ring[1][k];
-            if ((up && lo_eta) || (!up && hi_eta)) e2 = T(2) * e1 - c0;
-            o = o - sy * w.apply(e2, e1, c0, g1);
+        for (int c = 0; c < 3; ++c) {
+            const bool pos = d[c] >= T(0);
+            ad[c] = pos ? d[c] : -d[c];
+            a1[c] = pos ? own - E : own + E;
+            f1[c] = pos ? own + E : own - E;
+            a2[c] = pos ? own - 2 * E : own + 2 * E;
+            a2m[c] = pos ? own + 2 * E : own - 2 * E;
+            if (EDGE) {
+                edge_p[c] = pos ? i == 1 : i == nx - 2;
+                edge_m[c] = pos ? i == nx - 2 : i == 1;
+            }
         }
-        out[k] = o;
+        if (EDGE) {
+            edge1 = i == 1;
+            edge3 = i == nx - 2;
+        }
     }
-    __syncthreads();
+};
+
+template <typename T>
+__device__ __forceinline__ T lds_at(const T* row, uint32_t byte_offset)
+{
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(row) + byte_offset);
 }
+
+// LDS of one wavefront.
+template <typename T>
+struct WaveLds {
+    T xs[8][kRowLds];                 // one row of each moving population, for the xi stencils
+    T hp[kRing][9][kWaveLanes];       // f-hat+ of rows t-4 .. t (lane-private); the slot of row ny keeps
+                                      // f-bar of row ny-2 for the lid row of the half step
+    T wb[2][9];                       // f-bar of columns 1 and nx-2 at the current half-step row
+    T wc[2][9];                       // f-hat(t+dt) of columns 1 and nx-2 at the current full-step row
+};
 
 template <typename T>
 __device__ __forceinline__ void publish(T (*w)[9], int i, int nx, const T (&x)[9])
@@ -119,15 +214,15 @@ __device__ __forceinline__ void wall_source(T (*w)[9], int i, int nx, const T (&
     for (int k = 0; k < 9; ++k) src[k] = interior ? own[k] : w[side][k];
 }
 
-template <typename T>
-__device__ __forceinline__ void half_step(const T (&fb)[9], T lam, T dt, T (&out)[9])
+template <typename T, typename V>
+__device__ __forceinline__ void half_step(const T (&fb)[9], V lam, V dt, T (&out)[9])
 {
     T P, ux, uy, e[9];
     moments(fb, P, ux, uy);
     equilibrium(P, ux, uy, e);
-    const HalfStep<T> hs(lam, dt);
+    const T b = T(half_coef(lam, dt));
 #pragma unroll
-    for (int k = 0; k < 9; ++k) out[k] = hs.a * fb[k] + hs.b * e[k];
+    for (int k = 0; k < 9; ++k) out[k] = fb[k] + b * (e[k] - fb[k]);
 }
 
 template <typename T>
@@ -145,248 +240,387 @@ __device__ __forceinline__ void residual_add(const T (&gn)[9], const T (&old)[3]
     acc[6] += (isfinite((double)ux) && isfinite((double)uy) && isfinite((double)P)) ? 0.0 : 1.0;
 }
 
-// LDS of one wavefront.
-template <typename T>
-struct WaveLds {
-    T xs[8][kWaveLanes + 2 * kPad];   // one row of each moving population, for the xi stencils
-    T wb[2][9];                       // f-bar of columns 1 and nx-2 at the current half-step row
-    T wc[2][9];                       // f-hat(t+dt) of columns 1 and nx-2 at the current full-step row
-    T keep_b[9][kWaveLanes];          // f-bar of row ny-2, source of the lid row
-    T keep_c[9][kWaveLanes];          // f-hat(t+dt) of row ny-2, source of the lid row
-};
-
+// One work item.  Register ring slot of row t - d at unrolled phase R:
+// (R + 5 - d) % 5 for f-bar+ and lambda (d = 0..4), (R + 10 - d) % 5 for
+// f(t + dt/2) (d = 2..6); with one row per trip R is 0 and the rings move.
 template <int PREC, bool RES, bool EDGE>
-__device__ __forceinline__ void fused_item(const StepArgs& a, const StripItem& it, const CavityDesc& c,
-                                           WaveLds<typename Storage<PREC>::T>& sh, double (&acc)[kPartials])
-{
+struct March {
     using S = Storage<PREC>;
     using T = typename S::T;
-    auto& xs = sh.xs;
-    auto& wb = sh.wb;
-    auto& wc = sh.wc;
-    auto& keep_b = sh.keep_b;
-    auto& keep_c = sh.keep_c;
+    using V = typename S::V;
+    using F = typename S::F;
+    using L = typename S::L;
 
-    const int lane = threadIdx.x;
-    const int nx = c.nx, ny = c.ny;
-    const int i = it.i0 - kHaloCols + lane;
-    // halo lanes outside the grid read the nearest column; their results are never used
-    const int ic = min(max(i, 0), nx - 1);
-    const bool out_col = i >= it.i0 && i < it.i1;
-    const bool walls_b = it.i0 <= 2 || it.i1 >= nx - 2;
-    const bool walls_c = it.i0 == 0 || it.i1 == nx;
-    const PowerLaw<T> pl(c);
-    const T dt = pl.dt, ulid = T(c.u_lid);
-    const T sy_b = T(0.5) * dt * T(c.inv2deta), sy_c = dt * T(c.inv2deta);
-    const T sx_b = T(0.5) * dt * T(c.inv2dxi), sx_c = dt * T(c.inv2dxi);
-    const MixedWeights<T> mw(T(c.mix));
+    static constexpr int sg(int R, int d) { return (R + 2 * kRing - d) % kRing; }
+    static constexpr int sf(int R, int d) { return (R + 3 * kRing - d) % kRing; }
 
-    // uniform base of each plane (64-bit, scalar) plus a 32-bit row offset per lane
-    const auto* fin = static_cast<const typename S::F*>(a.f_in) + c.f_off;
-    const auto* lin = static_cast<const typename S::L*>(a.l_in) + c.l_off;
-    auto* fout = static_cast<typename S::F*>(a.f_out) + c.f_off;
-    auto* lout = static_cast<typename S::L*>(a.l_out) + c.l_off;
-    const int64_t plane = c.plane;
-    const T* geo = geo_of<T>(a) + c.geo_off;
-    const uint32_t lseed = S::kStochastic ? mix32(a.seed_ctr[0] ^ mix32(a.step)) : 0u;
+    const StepArgs& a;
+    const StripItem& it;
+    const CavityDesc& c;
+    WaveLds<T>& sh;
+    double (&acc)[kPartials];
 
-    // c_kx - c_ky s_i: the contravariant xi-velocity is a_j times this (Eqs. 3.2-3.8.2)
-    const T s = geo[ny + ic];
-    T adk[9];
-    bool pos[9], edge[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const T d = T(cxk(k)) - T(cyk(k)) * s;
-        pos[k] = d >= T(0);
-        adk[k] = pos[k] ? d : -d;
-        edge[k] = pos[k] ? (i == 1) : (i == nx - 2);
-    }
+    int lane, nx, ny, i, ic, j0, j1, qlo, qhi, t_begin, t_last;
+    bool out_col, walls_b, walls_c;
+    PowerLaw<V> pl;
+    V dtv;
+    T ulid, sx_b, sy_b, sx_c, sy_c;
+    T eps;
+    const T* geo;
+    XiLane<T, EDGE> xl;
+    __amdgpu_buffer_rsrc_t rf_in, rf_out, rl_in, rl_out;
+    uint32_t fpb;          // bytes per distribution plane
+    uint32_t skey, ckey;   // stochastic rounding keys
+    int pitch;
 
-    T gbp[5][9], fh[5][9], lamr[5];
-#pragma unroll
-    for (int r = 0; r < 5; ++r) {
-        lamr[r] = T(1);
-#pragma unroll
-        for (int k = 0; k < 9; ++k) gbp[r][k] = fh[r][k] = T(0);
-    }
-    T mom0[3] = {0, 0, 0};
+    T gbp[kRing][9];       // f-bar+ (Eq. 2.16) of rows t-4 .. t
+    T fh[kRing][9];        // f(t + dt/2) of rows t-6 .. t-2
+    V lam[kRing];          // lambda of rows t-4 .. t
+    F gn_[9];              // f-hat of row t + 1, in flight
+    L ln_;
 
-    const int j0 = it.j0, j1 = it.j1;
-    const int qlo = max(j0 - 2, 0), qhi = min(j1 + 1, ny - 1);
-    const int t_begin = max(j0 - 4, 0), t_end = j1 + 3, t_last = min(t_end, ny - 1);
-
-    // row t_begin, fetched ahead of the loop
-    T gn_[9], ln_;
+    __device__ __forceinline__ March(const StepArgs& a_, const StripItem& it_, const CavityDesc& c_, WaveLds<T>& sh_,
+                                     double (&acc_)[kPartials])
+        : a(a_), it(it_), c(c_), sh(sh_), acc(acc_), pl(c_),
+          xl(threadIdx.x, it_.i0 - kHaloCols + (int)threadIdx.x, c_.nx,
+             geo_of<T>(a_)[c_.geo_off + c_.ny + min(max(it_.i0 - kHaloCols + (int)threadIdx.x, 0), c_.nx - 1)])
     {
-        const uint32_t o = (uint32_t)(t_begin * c.pitch + ic);
+        lane = threadIdx.x;
+        nx = c.nx;
+        ny = c.ny;
+        pitch = c.pitch;
+        i = it.i0 - kHaloCols + lane;
+        // halo lanes outside the grid read the nearest column; their results are never used
+        ic = min(max(i, 0), nx - 1);
+        out_col = i >= it.i0 && i < it.i1;
+        walls_b = it.i0 <= 2 || it.i1 >= nx - 2;
+        walls_c = it.i0 == 0 || it.i1 == nx;
+        j0 = it.j0;
+        j1 = it.j1;
+        qlo = max(j0 - 2, 0);
+        qhi = min(j1 + 1, ny - 1);
+        dtv = V(c.dt);
+        const T dt = T(c.dt);
+        ulid = T(c.u_lid);
+        sy_b = T(0.5) * dt * T(c.inv2deta);
+        sy_c = dt * T(c.inv2deta);
+        sx_b = T(0.5) * dt * T(c.inv2dxi);
+        sx_c = dt * T(c.inv2dxi);
+        eps = T(c.mix);
+        geo = geo_of<T>(a) + c.geo_off;
+        fpb = (uint32_t)c.plane * (uint32_t)sizeof(F);
+        rf_in = buffer_of(static_cast<const F*>(a.f_in) + c.f_off, 9u * fpb);
+        rf_out = buffer_of(static_cast<F*>(a.f_out) + c.f_off, 9u * fpb);
+        rl_in = buffer_of(static_cast<const L*>(a.l_in) + c.l_off, (uint32_t)c.plane * (uint32_t)sizeof(L));
+        rl_out = buffer_of(static_cast<L*>(a.l_out) + c.l_off, (uint32_t)c.plane * (uint32_t)sizeof(L));
+        skey = S::kStochastic ? step_key(a.seed_ctr[0], a.step) : 0u;
+        ckey = S::kStochastic ? cavity_key(it.cav) : 0u;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) gn_[k] = S::load(fin + k * plane, o, k);
-        ln_ = T(lin[o]);
+        for (int r = 0; r < kRing; ++r) {
+            lam[r] = V(1);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) gbp[r][k] = fh[r][k] = T(0);
+        }
+        t_begin = max(j0 - 4, 0);
+        // rows up to ny - 1 are read; the lid row of the output is made with row ny - 2
+        const int t_end = j1 == ny ? ny + 2 : j1 + 3;
+        t_last = min(t_end, ny - 1);
+        fetch(t_begin);
+        march(t_begin, t_end);
     }
 
-#pragma unroll 1
-    for (int t = t_begin; t <= t_end; ++t) {
-        T g[9], lam_old = ln_;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) g[k] = gn_[k];
-        // fetch row t + 1 now; it is consumed in the next iteration
-        if (t + 1 <= t_last) {
-            const uint32_t o = (uint32_t)((t + 1) * c.pitch + ic);
-#pragma unroll
-            for (int k = 0; k < 9; ++k) gn_[k] = S::load(fin + k * plane, o, k);
-            ln_ = T(lin[o]);
-        }
-        // f-hat of row t - 4 for stage C (read 4 rows ago, now an L2 hit)
-        const int p = t - 4;
-        const bool do_c = p >= j0 && p < j1;
-        T gc[9];
-        if (do_c) {
-            const uint32_t o = (uint32_t)(p * c.pitch + ic);
-#pragma unroll
-            for (int k = 0; k < 9; ++k) gc[k] = S::load(fin + k * plane, o, k);
-        }
+    // LDS ring slot of row r (a run-time index: the LDS ring is not moved when
+    // the register rings are)
+    __device__ __forceinline__ int hslot(int r) const { return (r - t_begin + 2 * kRing) % kRing; }
 
-        // ---------------------------------------------------------- A: row t
+    __device__ __forceinline__ uint32_t foff(int row) const { return (uint32_t)(row * pitch + ic) * (uint32_t)sizeof(F); }
+    __device__ __forceinline__ uint32_t loff(int row) const { return (uint32_t)(row * pitch + ic) * (uint32_t)sizeof(L); }
+
+    __device__ __forceinline__ void fetch(int row)
+    {
+        const uint32_t vo = foff(row);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) gn_[k] = Buf<F>::ld(rf_in, vo, (uint32_t)k * fpb);
+        ln_ = Buf<L>::ld(rl_in, loff(row), 0u);
+    }
+
+    // old moments of row `row` (residual only)
+    __device__ __forceinline__ void old_moments(int row, T (&m)[3]) const
+    {
+        const uint32_t vo = foff(row);
+        T g[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) g[k] = S::cvt(Buf<F>::ld(rf_in, vo, (uint32_t)k * fpb), k);
+        moments(g, m[0], m[1], m[2]);
+    }
+
+    __device__ __forceinline__ void store_row(int row, const T (&x)[9]) const
+    {
+        const uint32_t vo = foff(row);
+        const NodeWords nw(skey, ckey, (uint32_t)(row * pitch + i));
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Buf<F>::st(encode_state<S>(x[k], k, &nw), rf_out, vo, (uint32_t)k * fpb);
+    }
+
+    // out[k] = base[k] - sx * a_j d_k * D_xi - sy * D_eta for the moving
+    // populations of one row, where D are the signed mixed differences: xi
+    // neighbours from the LDS row, eta neighbours from ring slots s[0..4]
+    // (rows r-2 .. r+2).  mx carries sx * a_j, my carries sy.
+    template <int S0, int S1, int S2, int S3, int S4>
+    __device__ __forceinline__ void transport(const T (&ring)[kRing][9], const T (&base)[9], const MixedWeights<T>& mx,
+                                              const MixedWeights<T>& my, T (&out)[9])
+    {
+        auto& xs = sh.xs;
+#pragma unroll
+        for (int k = 1; k < 9; ++k) xs[k - 1][lane + kPad] = ring[S2][k];
+        __syncthreads();
+        out[0] = base[0];
+#pragma unroll
+        for (int k = 1; k < 9; ++k) {
+            const T* row = xs[k - 1];
+            const T c0 = ring[S2][k];
+            T a1, a2, f1, w;
+            bool edge = false;
+            constexpr uint32_t E = sizeof(T);
+            if (k == 1 || k == 3) {
+                const bool pos = k == 1;
+                a1 = lds_at(row, pos ? xl.own - E : xl.own + E);
+                a2 = lds_at(row, pos ? xl.own - 2 * E : xl.own + 2 * E);
+                f1 = lds_at(row, pos ? xl.own + E : xl.own - E);
+                w = T(1);
+                if (EDGE) edge = pos ? xl.edge1 : xl.edge3;
+            } else {
+                const int pr = (k == 2 || k == 4) ? 0 : ((k == 5 || k == 7) ? 1 : 2);
+                const bool first = k == 2 || k == 5 || k == 6;
+                a1 = lds_at(row, first ? xl.a1[pr] : xl.f1[pr]);
+                a2 = lds_at(row, first ? xl.a2[pr] : xl.a2m[pr]);
+                f1 = lds_at(row, first ? xl.f1[pr] : xl.a1[pr]);
+                w = xl.ad[pr];
+                if (EDGE) edge = first ? xl.edge_p[pr] : xl.edge_m[pr];
+            }
+            if (EDGE) a2 = edge ? T(2) * a1 - c0 : a2;
+            T o = base[k] - w * mx.apply(a2, a1, c0, f1);
+            if (moves_up(k)) o = o - my.apply(ring[S0][k], ring[S1][k], c0, ring[S3][k]);
+            if (moves_down(k)) o = o - my.apply(ring[S4][k], ring[S3][k], c0, ring[S1][k]);
+            out[k] = o;
+        }
+        __syncthreads();
+    }
+
+    // Rows outside [1, ny-2] of a ring take the linear extrapolation 2 a1 - c0,
+    // which turns the second-order one-sided difference into the first-order
+    // one (the eta counterpart of the EDGE columns).
+    template <int S0, int S1, int S2, int S3, int S4>
+    __device__ __forceinline__ void eta_ghosts(T (&ring)[kRing][9], bool lo, bool hi)
+    {
+        if (lo) {
+#pragma unroll
+            for (int k = 1; k < 9; ++k)
+                if (moves_up(k)) ring[S0][k] = T(2) * ring[S1][k] - ring[S2][k];
+        }
+        if (hi) {
+#pragma unroll
+            for (int k = 1; k < 9; ++k)
+                if (moves_down(k)) ring[S4][k] = T(2) * ring[S3][k] - ring[S2][k];
+        }
+    }
+
+    template <int R>
+    __device__ __forceinline__ void row(int t)
+    {
+        // ------------------------------------------------------------ A: row t
         if (t <= ny - 1) {
-            T P, ux, uy, e[9];
+            const int hs = hslot(t);
+            T g[9], e[9], d[9], P, ux, uy;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) g[k] = S::cvt(gn_[k], k);
+            const V lam_old = V(ln_);
+            if (t + 1 <= t_last) fetch(t + 1);   // consumed by the next row
             moments(g, P, ux, uy);
             equilibrium(P, ux, uy, e);
-            const T lam = relaxation_time(g, e, lam_old, pl);
-            const Collision<T> coll(lam, dt);
 #pragma unroll
-            for (int k = 0; k < 9; ++k) gbp[4][k] = coll.a_bar * g[k] + coll.b_bar * e[k];
-            lamr[4] = lam;
+            for (int k = 0; k < 9; ++k) d[k] = e[k] - g[k];
+            const V l = relaxation_time_d(d, lam_old, pl);
+            const Relax<V> rx(l, dtv);
+            const T b_hat = T(rx.b_hat), b_bar = T(rx.b_bar);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                gbp[sg(R, 0)][k] = g[k] + b_bar * d[k];
+                sh.hp[hs][k][lane] = g[k] + b_hat * d[k];
+            }
+            lam[sg(R, 0)] = l;
+            if (out_col && t >= j0 && t < j1) Buf<L>::st(L(l), rl_out, loff(t), 0u);
         }
 
-        // ---------------------------------------------------------- B: row t - 2
+        // ------------------------------------------------------------ B: row t - 2
         const int q = t - 2;
         if (q >= qlo && q <= qhi) {
             T fb[9];
             if (q >= 1 && q <= ny - 2) {
-                transport_row<T, EDGE>(xs, lane, gbp, gbp[2], adk, pos, edge, q == 1, q == ny - 2, sx_b * geo[q], sy_b,
-                                       mw, fb);
+                eta_ghosts<sg(R, 4), sg(R, 3), sg(R, 2), sg(R, 1), sg(R, 0)>(gbp, q == 1, q == ny - 2);
+                const MixedWeights<T> mx(eps, sx_b * geo[q]), my(eps, sy_b);
+                transport<sg(R, 4), sg(R, 3), sg(R, 2), sg(R, 1), sg(R, 0)>(gbp, gbp[sg(R, 2)], mx, my, fb);
                 if (walls_b) {
-                    publish(wb, i, nx, fb);
+                    publish(sh.wb, i, nx, fb);
                     __syncthreads();
                     if (i == 0 || i == nx - 1) {
                         T src[9];
-                        wall_source(wb, i, nx, fb, src);
+                        wall_source(sh.wb, i, nx, fb, src);
                         extrapolate(src, T(0), fb);
                     }
                 }
-                if (q == 1) {   // bottom wall row from row 1 (Eq. 1.5: at rest)
+                if (q == 1) {   // bottom wall row (row t - 3) from row 1 (Eq. 1.5: at rest)
                     T src[9], fb0[9], out0[9];
-                    wall_source(wb, i, nx, fb, src);
+                    wall_source(sh.wb, i, nx, fb, src);
                     extrapolate(src, T(0), fb0);
-                    half_step(fb0, lamr[1], dt, out0);
+                    half_step(fb0, lam[sg(R, 3)], dtv, out0);
 #pragma unroll
-                    for (int k = 0; k < 9; ++k) fh[3][k] = out0[k];
+                    for (int k = 0; k < 9; ++k) fh[sf(R, 3)][k] = out0[k];
                 }
-                if (q == ny - 2)
+                if (q == ny - 2) {   // source of the lid row, kept in the free f-hat+ slot of row t = ny
+                    const int hs = hslot(t);
 #pragma unroll
-                    for (int k = 0; k < 9; ++k) keep_b[k][lane] = fb[k];
-            } else if (q == ny - 1) {   // lid row from row ny - 2
+                    for (int k = 0; k < 9; ++k) sh.hp[hs][k][lane] = fb[k];
+                }
+            } else if (q == ny - 1) {   // lid row from row ny - 2 (kept one row ago)
                 T own[9], src[9];
+                const int hs = hslot(t - 1);
 #pragma unroll
-                for (int k = 0; k < 9; ++k) own[k] = keep_b[k][lane];
-                wall_source(wb, i, nx, own, src);
+                for (int k = 0; k < 9; ++k) own[k] = sh.hp[hs][k][lane];
+                wall_source(sh.wb, i, nx, own, src);
                 extrapolate(src, ulid, fb);
             }
             if (q >= 1) {
                 T out[9];
-                half_step(fb, lamr[2], dt, out);
+                half_step(fb, lam[sg(R, 2)], dtv, out);
 #pragma unroll
-                for (int k = 0; k < 9; ++k) fh[4][k] = out[k];
+                for (int k = 0; k < 9; ++k) fh[sf(R, 2)][k] = out[k];
             }
         }
 
-        // ---------------------------------------------------------- C: row t - 4
-        if (do_c) {
-            const uint32_t node = (uint32_t)(p * c.pitch + ic);
-            if (out_col) lout[node] = (typename S::L)lamr[0];
-            T old[3];
-            moments(gc, old[0], old[1], old[2]);
-            if (p >= 1 && p <= ny - 2) {
-                // f-hat+ of row p (Eq. 2.15) from its f-hat and the lambda of stage A
-                T e[9], hp[9], gn[9];
-                equilibrium(old[0], old[1], old[2], e);
-                const Collision<T> coll(lamr[0], dt);
+        // ------------------------------------------------------------ C: row t - 4
+        const int p = t - 4;
+        if (p >= j0 && p < j1 && p >= 1 && p <= ny - 2) {
+            T hp[9], gn[9];
+            const int hs = hslot(p);
 #pragma unroll
-                for (int k = 0; k < 9; ++k) hp[k] = coll.a_hat * gc[k] + coll.b_hat * e[k];
-                transport_row<T, EDGE>(xs, lane, fh, hp, adk, pos, edge, p == 1, p == ny - 2, sx_c * geo[p], sy_c, mw, gn);
-                if (walls_c) {
-                    publish(wc, i, nx, gn);
-                    __syncthreads();
-                    if (i == 0 || i == nx - 1) {
-                        T src[9];
-                        wall_source(wc, i, nx, gn, src);
-                        extrapolate(src, T(0), gn);
+            for (int k = 0; k < 9; ++k) hp[k] = sh.hp[hs][k][lane];
+            eta_ghosts<sf(R, 6), sf(R, 5), sf(R, 4), sf(R, 3), sf(R, 2)>(fh, p == 1, p == ny - 2);
+            const MixedWeights<T> mx(eps, sx_c * geo[p]), my(eps, sy_c);
+            transport<sf(R, 6), sf(R, 5), sf(R, 4), sf(R, 3), sf(R, 2)>(fh, hp, mx, my, gn);
+            if (walls_c) {
+                publish(sh.wc, i, nx, gn);
+                __syncthreads();
+                if (i == 0 || i == nx - 1) {
+                    T src[9];
+                    wall_source(sh.wc, i, nx, gn, src);
+                    extrapolate(src, T(0), gn);
+                }
+            }
+            if (out_col) {
+                store_row(p, gn);
+                if (RES) {
+                    T old[3];
+                    old_moments(p, old);
+                    residual_add(gn, old, acc);
+                }
+            }
+            if (p == 1 && j0 == 0) {   // bottom wall row from row 1
+                T src[9], g0[9];
+                wall_source(sh.wc, i, nx, gn, src);
+                extrapolate(src, T(0), g0);
+                if (out_col) {
+                    store_row(0, g0);
+                    if (RES) {
+                        T old[3];
+                        old_moments(0, old);
+                        residual_add(g0, old, acc);
                     }
                 }
+            }
+            if (p == ny - 2 && j1 == ny) {   // lid row from row ny - 2
+                T src[9], gl[9];
+                wall_source(sh.wc, i, nx, gn, src);
+                extrapolate(src, ulid, gl);
                 if (out_col) {
-                    const uint32_t ns = S::kStochastic ? node_seed(lseed, it.cav, p, i) : 0u;
-#pragma unroll
-                    for (int k = 0; k < 9; ++k) store_state<S>(fout + k * plane, node, k, gn[k], ns);
-                    if (RES) residual_add(gn, old, acc);
-                }
-                if (p == 1 && j0 == 0) {   // bottom wall row from row 1
-                    T src[9], g0[9];
-                    wall_source(wc, i, nx, gn, src);
-                    extrapolate(src, T(0), g0);
-                    if (out_col) {
-                        const uint32_t ns = S::kStochastic ? node_seed(lseed, it.cav, 0, i) : 0u;
-#pragma unroll
-                        for (int k = 0; k < 9; ++k) store_state<S>(fout + k * plane, (uint32_t)ic, k, g0[k], ns);
-                        if (RES) residual_add(g0, mom0, acc);
+                    store_row(ny - 1, gl);
+                    if (RES) {
+                        T old[3];
+                        old_moments(ny - 1, old);
+                        residual_add(gl, old, acc);
                     }
                 }
-                if (p == ny - 2)
-#pragma unroll
-                    for (int k = 0; k < 9; ++k) keep_c[k][lane] = gn[k];
-            } else if (p == ny - 1) {   // lid row from row ny - 2
-                T own[9], src[9], gn[9];
-#pragma unroll
-                for (int k = 0; k < 9; ++k) own[k] = keep_c[k][lane];
-                wall_source(wc, i, nx, own, src);
-                extrapolate(src, ulid, gn);
-                if (out_col) {
-                    const uint32_t ns = S::kStochastic ? node_seed(lseed, it.cav, p, i) : 0u;
-#pragma unroll
-                    for (int k = 0; k < 9; ++k) store_state<S>(fout + k * plane, node, k, gn[k], ns);
-                    if (RES) residual_add(gn, old, acc);
-                }
-            } else {   // p == 0: stored with row 1; keep its old moments
-#pragma unroll
-                for (int m = 0; m < 3; ++m) mom0[m] = old[m];
             }
         }
+    }
 
-        // ---------------------------------------------------------- rings
+    __device__ __forceinline__ void rotate()
+    {
+        // one row per trip: move every ring one slot so that phase 0 fits the next row
+        T tg[9], tf[9];
+        const V tl = lam[0];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            lamr[r] = lamr[r + 1];
+        for (int k = 0; k < 9; ++k) {
+            tg[k] = gbp[0][k];
+            tf[k] = fh[0][k];
+        }
+#pragma unroll
+        for (int r = 0; r < kRing - 1; ++r) {
+            lam[r] = lam[r + 1];
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
                 gbp[r][k] = gbp[r + 1][k];
                 fh[r][k] = fh[r + 1][k];
             }
         }
+        lam[kRing - 1] = tl;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            gbp[kRing - 1][k] = tg[k];
+            fh[kRing - 1][k] = tf[k];
+        }
     }
-}
+
+    __device__ __forceinline__ void march(int t_begin, int t_end)
+    {
+        if constexpr (Tuning<PREC>::kUnroll == kRing) {
+#pragma unroll 1
+            for (int t = t_begin;; t += kRing) {
+                row<0>(t);
+                if (t + 1 > t_end) break;
+                row<1>(t + 1);
+                if (t + 2 > t_end) break;
+                row<2>(t + 2);
+                if (t + 3 > t_end) break;
+                row<3>(t + 3);
+                if (t + 4 > t_end) break;
+                row<4>(t + 4);
+                if (t + 5 > t_end) break;
+            }
+        } else {
+#pragma unroll 1
+            for (int t = t_begin; t <= t_end; ++t) {
+                row<0>(t);
+                rotate();
+            }
+        }
+    }
+};
 
 template <int PREC, bool RES>
-__global__ __launch_bounds__(kWaveLanes) void k_fused(StepArgs a, const StripItem* items, int w0, int nw)
+__global__ __launch_bounds__(kWaveLanes, Tuning<PREC>::kWaves) void k_fused(StepArgs a, const StripItem* items, int w0, int nw)
 {
-    const int w = w0 + xcd_order(blockIdx.x, nw);
+    const int w = w0 + (int)blockIdx.x;
     const StripItem it = items[w];
+    if (it.unit < 0) return;   // padding of a per-XCD queue
     const CavityDesc c = a.desc[it.cav];
     __shared__ WaveLds<typename Storage<PREC>::T> sh;
     double acc[kPartials] = {0, 0, 0, 0, 0, 0, 0};
     // waves that hold column 1 or nx-2 take the first-order one-sided points (Eq. 2.7 at walls)
-    if (it.i0 <= 5 || it.i1 >= c.nx - 5)
-        fused_item<PREC, RES, true>(a, it, c, sh, acc);
+    if (IFD_FUSED_ONE_PATH || it.i0 <= 5 || it.i1 >= c.nx - 5)
+        March<PREC, RES, true>(a, it, c, sh, acc);
     else
-        fused_item<PREC, RES, false>(a, it, c, sh, acc);
+        March<PREC, RES, false>(a, it, c, sh, acc);
     if (RES) {
         // wavefront sum in a fixed order
 #pragma unroll
@@ -394,7 +628,7 @@ __global__ __launch_bounds__(kWaveLanes) void k_fused(StepArgs a, const StripIte
             double v = acc[q5];
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWaveLanes);
-            if (threadIdx.x == 0) a.partial[(int64_t)w * kPartials + q5] = v;
+            if (threadIdx.x == 0) a.partial[(int64_t)it.unit * kPartials + q5] = v;
         }
     }
 }

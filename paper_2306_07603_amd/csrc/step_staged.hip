@@ -74,21 +74,25 @@ __global__ __launch_bounds__(kNodeBlock) void k_stage_a(StepArgs a, const NodeBl
     if (!locate(blocks, b0 + blockIdx.x, a.desc, c, r)) return;
     const auto* f = static_cast<const typename S::F*>(a.f_in);
     const auto* l = static_cast<const typename S::L*>(a.l_in);
-    T g[9], e[9], P, ux, uy;
+    using V = typename S::V;
+    T g[9], e[9], d[9], P, ux, uy;
 #pragma unroll
     for (int k = 0; k < 9; ++k) g[k] = S::load(f, c.f_off + k * c.plane + r.id, k);
     moments(g, P, ux, uy);
     equilibrium(P, ux, uy, e);
-    const T lam = relaxation_time(g, e, T(l[c.l_off + r.id]), c);
-    const Collision<T> col(lam, T(c.dt));
+#pragma unroll
+    for (int k = 0; k < 9; ++k) d[k] = e[k] - g[k];
+    const V lam = relaxation_time_d(d, V(l[c.l_off + r.id]), PowerLaw<V>(c));
+    const Relax<V> rx(lam, V(c.dt));
+    const T b_hat = T(rx.b_hat), b_bar = T(rx.b_bar);
     T* hp = static_cast<T*>(a.hat_plus);
     T* bp = static_cast<T*>(a.bar_plus);
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-        hp[c.f_off + k * c.plane + r.id] = col.a_hat * g[k] + col.b_hat * e[k];
-        bp[c.f_off + k * c.plane + r.id] = col.a_bar * g[k] + col.b_bar * e[k];
+        hp[c.f_off + k * c.plane + r.id] = g[k] + b_hat * d[k];
+        bp[c.f_off + k * c.plane + r.id] = g[k] + b_bar * d[k];
     }
-    static_cast<T*>(a.lam_new)[c.l_off + r.id] = lam;
+    static_cast<T*>(a.lam_new)[c.l_off + r.id] = T(lam);
 }
 
 template <int PREC>
@@ -132,13 +136,14 @@ __global__ __launch_bounds__(kNodeBlock) void k_stage_bh(StepArgs a, const NodeB
 #pragma unroll
         for (int k = 0; k < 9; ++k) x[k] = fbar[c.f_off + k * c.plane + r.id];
     }
+    using V = typename Storage<PREC>::V;
     T P, ux, uy, e[9];
     moments(x, P, ux, uy);
     equilibrium(P, ux, uy, e);
-    const HalfStep<T> hs(static_cast<const T*>(a.lam_new)[c.l_off + r.id], T(c.dt));
+    const T b = T(half_coef(V(static_cast<const T*>(a.lam_new)[c.l_off + r.id]), V(c.dt)));
     T* fh = static_cast<T*>(a.bar_plus);   // f-bar+ is dead after stage B
 #pragma unroll
-    for (int k = 0; k < 9; ++k) fh[c.f_off + k * c.plane + r.id] = hs.a * x[k] + hs.b * e[k];
+    for (int k = 0; k < 9; ++k) fh[c.f_off + k * c.plane + r.id] = x[k] + b * (e[k] - x[k]);
 }
 
 template <int PREC>
@@ -158,14 +163,14 @@ __global__ __launch_bounds__(kNodeBlock) void k_stage_c(StepArgs a, const NodeBl
     auto* out = static_cast<typename S::F*>(a.f_out);
     const T* geo = geo_table<T>(a);
     const T dt = T(c.dt);
-    const uint32_t ns = S::kStochastic ? node_seed(mix32(a.seed_ctr[0] ^ mix32(a.step)), c.index, r.j, r.i) : 0u;
-    store_state<S>(out, c.f_off + r.id, 0, hp[c.f_off + r.id], ns);
+    const NodeWords nw(step_key(a.seed_ctr[0], a.step), cavity_key(c.index), (uint32_t)r.id);
+    out[c.f_off + r.id] = encode_state<S>(hp[c.f_off + r.id], 0, &nw);
 #pragma unroll 1
     for (int k = 1; k < 9; ++k) {
         const int64_t o = c.f_off + k * c.plane;
         const T v = hp[o + r.id] - dt * transport(fh + o, c, geo, r.i, r.j, k);
         hp[o + r.id] = v;
-        store_state<S>(out, o + r.id, k, v, ns);
+        out[o + r.id] = encode_state<S>(v, k, &nw);
     }
 }
 
@@ -187,9 +192,9 @@ __global__ __launch_bounds__(kNodeBlock) void k_stage_cb(StepArgs a, const NodeB
 #pragma unroll
     for (int k = 0; k < 9; ++k) xnb[k] = fnew[c.f_off + k * c.plane + nid];
     extrapolate(xnb, r.j == c.ny - 1 ? T(c.u_lid) : T(0), x);
-    const uint32_t ns = S::kStochastic ? node_seed(mix32(a.seed_ctr[0] ^ mix32(a.step)), c.index, r.j, r.i) : 0u;
+    const NodeWords nw(step_key(a.seed_ctr[0], a.step), cavity_key(c.index), (uint32_t)r.id);
 #pragma unroll
-    for (int k = 0; k < 9; ++k) store_state<S>(out, c.f_off + k * c.plane + r.id, k, x[k], ns);
+    for (int k = 0; k < 9; ++k) out[c.f_off + k * c.plane + r.id] = encode_state<S>(x[k], k, &nw);
 }
 
 // Eq. (2.19) partial sums over one node block, from the moments of f-hat

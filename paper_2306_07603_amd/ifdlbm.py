@@ -20,7 +20,8 @@ except ImportError:
     torch = None
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libifdlbm.so")
+# IFDLBM_LIB may name another build of the library (for A/B timing of build variants)
+LIB_PATH = os.environ.get("IFDLBM_LIB") or os.path.join(_PKG, "libifdlbm.so")
 
 IFDLBM_OK = 0
 IFDLBM_EINVAL = -1
@@ -53,7 +54,7 @@ class ifdlbm_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("cfl", ctypes.c_double), ("mix", ctypes.c_double),
                 ("rho0", ctypes.c_double), ("gamma_min", ctypes.c_double), ("residual_every", ctypes.c_int32),
                 ("kernel", ctypes.c_int32), ("batched", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
-                ("dt_rule", ctypes.c_int32), ("hip_stream", ctypes.c_void_p)]
+                ("dt_rule", ctypes.c_int32), ("segment_rows", ctypes.c_int32), ("hip_stream", ctypes.c_void_p)]
 
 
 class ifdlbm_info_t(ctypes.Structure):
@@ -61,6 +62,18 @@ class ifdlbm_info_t(ctypes.Structure):
                 ("state_bytes", ctypes.c_int64), ("alg_bytes_per_node", ctypes.c_double),
                 ("launches_per_step", ctypes.c_int32), ("work_items", ctypes.c_int64)]
 
+
+class ifdlbm_regime_t(ctypes.Structure):
+    _fields_ = [("regime", ctypes.c_int32), ("mean", ctypes.c_double), ("rel_amplitude", ctypes.c_double),
+                ("f_main", ctypes.c_double), ("f_second", ctypes.c_double), ("harmonic_fraction", ctypes.c_double),
+                ("second_fraction", ctypes.c_double)]
+
+
+IFDLBM_REGIME_STEADY = 0
+IFDLBM_REGIME_PERIODIC = 1
+IFDLBM_REGIME_QUASI_PERIODIC = 2
+IFDLBM_REGIME_APERIODIC = 3
+REGIMES = {0: "steady", 1: "periodic", 2: "quasi-periodic", 3: "aperiodic"}
 
 _lib = None
 _D = ctypes.POINTER(ctypes.c_double)
@@ -91,6 +104,12 @@ def lib():
         L.ifdlbm_info.argtypes = [_H, ctypes.POINTER(ifdlbm_info_t)]
         L.ifdlbm_gradient.argtypes = [ctypes.POINTER(ifdlbm_cavity), ctypes.POINTER(ifdlbm_options), ctypes.c_int64,
                                       ctypes.c_int32, _D, _D]
+        L.ifdlbm_record.argtypes = [_H, ctypes.c_int32, ctypes.c_int32]
+        L.ifdlbm_get_record.argtypes = [_H, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_int64), _D, _D, _D]
+        L.ifdlbm_time_step.argtypes = [_H, ctypes.c_int32, _D]
+        L.ifdlbm_classify.argtypes = [_D, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                      ctypes.POINTER(ifdlbm_regime_t)]
         L.ifdlbm_destroy.argtypes = [_H]
         L.ifdlbm_destroy.restype = None
         L.ifdlbm_strerror.argtypes = [ctypes.c_int]
@@ -135,7 +154,10 @@ class Cavity:
 def ifdlbm_default_options(**overrides) -> ifdlbm_options:
     o = ifdlbm_options()
     _check(lib().ifdlbm_default_options(ctypes.byref(o)))
+    names = {f[0] for f in ifdlbm_options._fields_}
     for k, v in overrides.items():
+        if k not in names:
+            raise TypeError("unknown option %r" % k)
         if k == "precision" and isinstance(v, str):
             v = PRECISIONS[v]
         if k == "kernel" and isinstance(v, str):
@@ -260,6 +282,36 @@ def ifdlbm_gradient(cavity: Cavity, options: Optional[ifdlbm_options] = None, n_
     _check(lib().ifdlbm_gradient(ctypes.byref(cavity.c()), ctypes.byref(options), int(n_steps), int(objective),
                                  ctypes.byref(J), _dptr(grad)))
     return J.value, grad
+
+
+def ifdlbm_record(h: Handle, every: int, capacity: int = 0) -> None:
+    _check(lib().ifdlbm_record(h.ptr, every, capacity))
+
+
+def ifdlbm_get_record(h: Handle, cav: int, max_samples: int = 1 << 20):
+    """(steps, u, v, ke) of the recorded samples of cavity cav, oldest first."""
+    n = ctypes.c_int32(0)
+    steps = np.zeros(max_samples, dtype=np.int64)
+    u, v, ke = (np.zeros(max_samples) for _ in range(3))
+    _check(lib().ifdlbm_get_record(h.ptr, cav, max_samples, ctypes.byref(n),
+                                   steps.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dptr(u), _dptr(v), _dptr(ke)))
+    m = n.value
+    return steps[:m].copy(), u[:m].copy(), v[:m].copy(), ke[:m].copy()
+
+
+def ifdlbm_time_step(h: Handle, cav: int) -> float:
+    dt = ctypes.c_double(0.0)
+    _check(lib().ifdlbm_time_step(h.ptr, cav, ctypes.byref(dt)))
+    return dt.value
+
+
+def ifdlbm_classify(x, dt_sample: float, steady_tol: float = 1e-6) -> dict:
+    a = np.ascontiguousarray(x, dtype=np.float64)
+    r = ifdlbm_regime_t()
+    _check(lib().ifdlbm_classify(_dptr(a), a.size, dt_sample, steady_tol, ctypes.byref(r)))
+    out = {f[0]: getattr(r, f[0]) for f in ifdlbm_regime_t._fields_}
+    out["name"] = REGIMES[r.regime]
+    return out
 
 
 def ifdlbm_destroy(h: Handle) -> None:

@@ -34,6 +34,12 @@ def test_default_options():
     o = M.ifdlbm_default_options()
     assert o.precision == M.IFDLBM_FP64 and o.cfl == 0.5 and o.mix == 0.5 and o.rho0 == 1.0
     assert o.gamma_min == 1e-6 and o.residual_every == 1 and o.batched == 1 and o.graph_steps == 0
+    assert o.segment_rows == 0 and o.dt_rule == M.IFDLBM_DT_CONTRAVARIANT
+
+
+def test_unknown_option_name_is_an_error():
+    with pytest.raises(TypeError):
+        M.ifdlbm_default_options(segment_row=64)
 
 
 BAD_CAVITIES = [
@@ -44,6 +50,8 @@ BAD_CAVITIES = [
     M.Cavity(17, 17, -1.0, 1.0, 60.0),     # Re <= 0
     M.Cavity(17, 17, 100.0, 1.0, 60.0, 0.0),   # lid at rest: Re of Eq. (2.15.1) undefined
     M.Cavity(17, 17, float("nan"), 1.0, 60.0),
+    M.Cavity(5793, 5793, 100.0, 1.0, 60.0),   # nine FP64 planes would span 4 GiB or more
+    M.Cavity(32768, 5, 100.0, 1.0, 60.0),     # n_xi beyond 16-bit column indices
 ]
 
 
@@ -55,7 +63,8 @@ def test_create_rejects_bad_cavity(cav):
 
 
 @pytest.mark.parametrize("field,value", [("cfl", 0.0), ("mix", 1.5), ("gamma_min", 0.0), ("residual_every", 0),
-                                         ("precision", 7), ("kernel", 9), ("graph_steps", 3)])
+                                         ("precision", 7), ("kernel", 9), ("graph_steps", 3),
+                                         ("segment_rows", 15), ("segment_rows", 5000), ("dt_rule", 2)])
 def test_create_rejects_bad_options(field, value):
     o = M.ifdlbm_default_options(**{field: value})
     with pytest.raises(M.IfdlbmError) as e:
