@@ -68,6 +68,13 @@ typedef struct ifdlbm_s ifdlbm_t;
                                       the Courant number of the transformed Eqs. (3.6)-(3.7) (default)   */
 #define IFDLBM_DT_CARTESIAN     1  /* dt = cfl * min(dxi, deta) / c with c = 1                          */
 
+/* relaxation-time update of Step (2) (options.lambda_mode) */
+#define IFDLBM_LAMBDA_LAGGED   0   /* strain rate of Eqs. (2.12), (2.18) taken with the stored lambda of the
+                                      previous step: the explicit scheme of Section 3 (default)          */
+#define IFDLBM_LAMBDA_IMPLICIT 1   /* lambda solves lambda = mu(gamma(lambda)) / c_s^2 at each node with the
+                                      strain rate taken at that lambda (safeguarded Newton iteration);
+                                      steady states are those of the lagged scheme                      */
+
 /* cavity status (ifdlbm_status) */
 #define IFDLBM_STATUS_RUNNING       0
 #define IFDLBM_STATUS_CONVERGED     1
@@ -96,6 +103,7 @@ typedef struct {
     int32_t graph_steps;    /* > 0: replay steps from a captured HIP graph of this many steps         */
     int32_t dt_rule;        /* IFDLBM_DT_CONTRAVARIANT | IFDLBM_DT_CARTESIAN                          */
     int32_t segment_rows;   /* fused kernel: rows per work item, 0 = automatic, else in [16, 4096]    */
+    int32_t lambda_mode;    /* IFDLBM_LAMBDA_LAGGED (the paper's, default) | IFDLBM_LAMBDA_IMPLICIT    */
     void*   hip_stream;     /* hipStream_t to enqueue on, or NULL for the null stream                 */
 } ifdlbm_options;
 
@@ -111,7 +119,8 @@ typedef struct {
 } ifdlbm_info_t;
 
 /* Fills *opt with the defaults: FP64, cfl 0.5, mix 0.5, rho0 1, gamma_min 1e-6, residual_every 1,
-   fused kernel, batched, no graph, contravariant time-step rule, automatic segment rows, null stream. */
+   fused kernel, batched, no graph, contravariant time-step rule, automatic segment rows, lagged lambda,
+   null stream. */
 int ifdlbm_default_options(ifdlbm_options* opt);
 
 /* Validates cav[0..n_cav) and *opt, builds the metric terms of Eqs. (3.2)-(3.8.2) in FP64 on the host,
@@ -174,7 +183,8 @@ int ifdlbm_info(ifdlbm_t* h, ifdlbm_info_t* info);
    discrete step: every quantity of the step carries its three partial derivatives in FP64.  The parameters
    enter through the metric terms (Eqs. 3.2-3.8.2), the time step (dt_rule), K = U^(2-n)/Re (Eq. 2.15.1), the
    exponent of Eq. (1.4), the lid condition (Eq. 1.5) and the initial lambda.  Options cfl, mix, gamma_min,
-   dt_rule and hip_stream apply; precision, kernel, batching, graphs and residual_every do not.  Device memory
+   dt_rule and hip_stream apply; precision, kernel, batching, graphs and residual_every do not; lambda_mode must
+   be LAGGED.  Device memory
    (about 100 doubles per node) is allocated and freed inside the call, which synchronises the stream.
    J and grad are caller-owned.  Errors: EINVAL, ENOMEM, EDEVICE. */
 int ifdlbm_gradient(const ifdlbm_cavity* cav, const ifdlbm_options* opt, int64_t n_steps, int32_t objective,

@@ -26,6 +26,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 CAVITY, COUETTE, PERIODIC = 0, 1, 2
 DT_CONTRAVARIANT, DT_CARTESIAN = 0, 1
+LAMBDA_LAGGED, LAMBDA_IMPLICIT = 0, 1
 
 
 def compile_source(src: str, out: str) -> str:
@@ -49,7 +50,8 @@ class _Params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("re", ctypes.c_double),
                 ("n", ctypes.c_double), ("theta_deg", ctypes.c_double), ("u_lid", ctypes.c_double),
                 ("cfl", ctypes.c_double), ("mix", ctypes.c_double), ("rho0", ctypes.c_double),
-                ("gamma_min", ctypes.c_double), ("bc_mode", ctypes.c_int), ("dt_rule", ctypes.c_int)]
+                ("gamma_min", ctypes.c_double), ("bc_mode", ctypes.c_int), ("dt_rule", ctypes.c_int),
+                ("lambda_mode", ctypes.c_int)]
 
 
 class _Derived(ctypes.Structure):
@@ -85,6 +87,8 @@ def load(path: str):
     L.orc_collide.argtypes = [_D, _D, ctypes.c_double, ctypes.c_double, _D, _D]
     L.orc_relaxation_time.argtypes = [_D, _D] + [ctypes.c_double] * 5
     L.orc_relaxation_time.restype = ctypes.c_double
+    L.orc_relaxation_time_implicit.argtypes = [_D, _D] + [ctypes.c_double] * 4
+    L.orc_relaxation_time_implicit.restype = ctypes.c_double
     return L
 
 
@@ -129,10 +133,11 @@ class Params:
     gamma_min: float = 1e-6
     bc_mode: int = CAVITY
     dt_rule: int = DT_CONTRAVARIANT
+    lambda_mode: int = LAMBDA_LAGGED
 
     def c(self) -> _Params:
         return _Params(self.nx, self.ny, self.re, self.n, self.theta_deg, self.u_lid, self.cfl,
-                       self.mix, self.rho0, self.gamma_min, self.bc_mode, self.dt_rule)
+                       self.mix, self.rho0, self.gamma_min, self.bc_mode, self.dt_rule, self.lambda_mode)
 
 
 def derive(p: Params) -> dict:
@@ -185,6 +190,11 @@ def collide(fh, feq, lam: float, dt: float):
 def relaxation_time(fh, feq, lam_old: float, dt: float, K: float, n: float, gamma_min: float) -> float:
     fh, feq = np.ascontiguousarray(fh, float), np.ascontiguousarray(feq, float)
     return lib().orc_relaxation_time(_ptr(fh), _ptr(feq), lam_old, dt, K, n, gamma_min)
+
+
+def relaxation_time_implicit(fh, feq, dt: float, K: float, n: float, gamma_min: float) -> float:
+    fh, feq = np.ascontiguousarray(fh, float), np.ascontiguousarray(feq, float)
+    return lib().orc_relaxation_time_implicit(_ptr(fh), _ptr(feq), dt, K, n, gamma_min)
 
 
 def node_xy(p: Params, i: int, j: int):

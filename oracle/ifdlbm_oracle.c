@@ -57,6 +57,10 @@
  *      incompressible model (u depends on grad P only); the extrapolation
  *      walls leak the pressure moment at a constant rate at steady state, so
  *      the raw E(P) falls only as 1/n while the gauge-fixed E(P) converges.
+ *  R20 (option) The lag of Step (2) can be removed: with lambda_mode
+ *      IMPLICIT, lambda is the fixed point of Step (2) at the node (the
+ *      strain rate taken with the lambda being solved for), Section 3 notes
+ *      the lag keeps the scheme explicit; the default is the paper's lag.
  */
 #include "ifdlbm_oracle.h"
 
@@ -132,6 +136,7 @@ int orc_derive(const orc_params* p, orc_derived* d)
     if (p->bc_mode != ORC_CAVITY && p->theta_deg != 90.0) return -1;
     if (p->bc_mode < ORC_CAVITY || p->bc_mode > ORC_PERIODIC) return -1;
     if (p->dt_rule != ORC_DT_CONTRAVARIANT && p->dt_rule != ORC_DT_CARTESIAN) return -1;
+    if (p->lambda_mode != ORC_LAMBDA_LAGGED && p->lambda_mode != ORC_LAMBDA_IMPLICIT) return -1;
     /* R11 */
     d->dxi = (p->bc_mode == ORC_CAVITY) ? 1.0 / (p->nx - 1) : 1.0 / p->nx;
     d->deta = (p->bc_mode == ORC_PERIODIC) ? 1.0 / p->ny : 1.0 / (p->ny - 1);
@@ -352,6 +357,51 @@ double orc_relaxation_time(const double fh[9], const double feq[9], double lam_o
     return mu / CS2;
 }
 
+/* Implicit Step (2): lambda = mu(gamma(lambda)) / c_s^2.  With f recovered
+ * from f-hat at the same lambda (Eq. 2.18), f - f_eq = 2 lambda (f-hat - f_eq)
+ * / (2 lambda + dt), so Eq. (2.12) gives D = -Pi / (c_s^2 (2 lambda + dt)),
+ * Pi = sum_k c_k c_k (f-hat_k - f_eq,k), and gamma^2 = 2 D:D = 2 Q / (c_s^4
+ * (2 lambda + dt)^2), Q = Pi:Pi = Pxx^2 + 2 Pxy^2 + Pyy^2.  The map lambda ->
+ * mu(gamma(lambda)) / c_s^2 is non-increasing for n >= 1 and, for n < 1,
+ * increasing, concave in (2 lambda + dt) up to the floor and bounded by
+ * K gamma_min^(n-1) / c_s^2; lambda minus it is negative at 0 and crosses zero
+ * once.  Bisection on [0, upper] to the resolution of a double. */
+static double implicit_map(double lam, double Q, double dt, double K, double n, double gamma_min)
+{
+    double s = 2.0 * lam + dt;
+    double gamma2 = 2.0 * Q / (CS2 * CS2 * s * s);
+    double floor2 = gamma_min * gamma_min;
+    return K * pow(gamma2 > floor2 ? gamma2 : floor2, 0.5 * (n - 1.0)) / CS2;
+}
+
+double orc_relaxation_time_implicit(const double fh[9], const double feq[9], double dt, double K, double n,
+                                    double gamma_min)
+{
+    double pxx = 0.0, pxy = 0.0, pyy = 0.0;
+    for (int k = 0; k < 9; ++k) {
+        double d = fh[k] - feq[k];
+        pxx += CX[k] * CX[k] * d;
+        pxy += CX[k] * CY[k] * d;
+        pyy += CY[k] * CY[k] * d;
+    }
+    double Q = pxx * pxx + 2.0 * pxy * pxy + pyy * pyy;
+    if (n == 1.0) return K / CS2;
+    double lo = 0.0, hi;
+    if (n > 1.0)
+        hi = implicit_map(0.0, Q, dt, K, n, gamma_min);   /* the map only falls from here */
+    else
+        hi = K * pow(gamma_min * gamma_min, 0.5 * (n - 1.0)) / CS2;   /* the floor caps the map */
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (mid - implicit_map(mid, Q, dt, K, n, gamma_min) < 0.0)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
 /* ---------------------------------------------------------- Step (1) */
 
 int orc_init(const orc_params* p, double* F, double* Lam)
@@ -401,7 +451,9 @@ static int one_step(const orc_params* p, const orc_derived* d, double* F, double
         for (int k = 0; k < 9; ++k) fh[k] = F[k * nn + id];
         orc_moments(fh, p->rho0, &P, &ux, &uy);
         orc_equilibrium(P, ux, uy, p->rho0, feq);
-        double lam = orc_relaxation_time(fh, feq, Lam[id], dt, d->K, p->n, p->gamma_min);
+        double lam = p->lambda_mode == ORC_LAMBDA_IMPLICIT
+                         ? orc_relaxation_time_implicit(fh, feq, dt, d->K, p->n, p->gamma_min)
+                         : orc_relaxation_time(fh, feq, Lam[id], dt, d->K, p->n, p->gamma_min);
         w->lam[id] = lam;
         orc_collide(fh, feq, lam, dt, fhp, fbp);
         for (int k = 0; k < 9; ++k) {

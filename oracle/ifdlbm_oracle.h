@@ -44,7 +44,15 @@ typedef struct {
     double gamma_min;   /* floor of the shear rate in Eq. (1.4)              */
     int    bc_mode;     /* ORC_CAVITY, ORC_COUETTE or ORC_PERIODIC           */
     int    dt_rule;     /* ORC_DT_CONTRAVARIANT or ORC_DT_CARTESIAN          */
+    int    lambda_mode; /* ORC_LAMBDA_LAGGED or ORC_LAMBDA_IMPLICIT          */
 } orc_params;
+
+/* lambda_mode values.  LAGGED: Step (2) evaluates the strain rate with the
+ * lambda stored with f-hat (the previous step's), the paper's explicit
+ * scheme.  IMPLICIT: lambda solves lambda = mu(gamma(lambda)) / c_s^2 at the
+ * node, with the strain rate of Eqs. (2.12) and (2.18) taken at that same
+ * lambda (solved by bisection to machine precision). */
+enum { ORC_LAMBDA_LAGGED = 0, ORC_LAMBDA_IMPLICIT = 1 };
 
 /* dt_rule values (reading R11).  CONTRAVARIANT: dt = cfl / max(|c_xi|/dxi,
  * |c_eta|/deta) over the grid, the Courant number of the transformed
@@ -85,6 +93,10 @@ void   orc_collide(const double fh[9], const double feq[9], double lam, double d
                    double fhat_plus[9], double fbar_plus[9]);
 double orc_relaxation_time(const double fh[9], const double feq[9], double lam_old, double dt,
                            double K, double n, double gamma_min);
+/* The implicit reading: the lambda for which orc_relaxation_time returns the
+ * lambda it was given (a fixed point), found by bisection. */
+double orc_relaxation_time_implicit(const double fh[9], const double feq[9], double dt, double K, double n,
+                                    double gamma_min);
 
 /* Eq. (3.8.1): physical position of node (i, j). */
 void orc_node_xy(const orc_params* p, int i, int j, double* x, double* y);

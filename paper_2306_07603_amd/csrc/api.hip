@@ -274,15 +274,16 @@ int enqueue_step(ifdlbm_s* h, bool residual, uint32_t local)
     a.step = local;
     const int prec = h->opt.precision;
     const bool staged = h->opt.kernel == IFDLBM_KERNEL_STAGED;
+    const bool impl = h->opt.lambda_mode == IFDLBM_LAMBDA_IMPLICIT;
     hipError_t e = hipSuccess;
     if (h->opt.batched) {
         e = staged ? launch_staged_step(prec, a, h->d_act_blocks, 0, (int)h->act_blocks.size(), residual, h->stream)
-                   : launch_fused_step(prec, a, h->d_act_sorted, 0, (int)h->act_sorted.size(), residual, h->stream);
+                   : launch_fused_step(prec, impl, a, h->d_act_sorted, 0, (int)h->act_sorted.size(), residual, h->stream);
     } else {
         for (int c = 0; c < h->n_cav && e == hipSuccess; ++c) {
             if (!h->unit_count[c]) continue;
             e = staged ? launch_staged_step(prec, a, h->d_act_blocks, h->unit_first[c], h->unit_count[c], residual, h->stream)
-                       : launch_fused_step(prec, a, h->d_act_items, h->unit_first[c], h->unit_count[c], residual, h->stream);
+                       : launch_fused_step(prec, impl, a, h->d_act_items, h->unit_first[c], h->unit_count[c], residual, h->stream);
         }
     }
     if (e == hipSuccess && residual)
@@ -466,6 +467,7 @@ int ifdlbm_default_options(ifdlbm_options* opt)
     opt->graph_steps = 0;
     opt->dt_rule = IFDLBM_DT_CONTRAVARIANT;
     opt->segment_rows = 0;
+    opt->lambda_mode = IFDLBM_LAMBDA_LAGGED;
     opt->hip_stream = nullptr;
     return IFDLBM_OK;
 }
@@ -484,6 +486,8 @@ int ifdlbm_create(const ifdlbm_cavity* cav, int32_t n_cav, const ifdlbm_options*
     if (o.dt_rule != IFDLBM_DT_CONTRAVARIANT && o.dt_rule != IFDLBM_DT_CARTESIAN) return fail(IFDLBM_EINVAL, "unknown dt_rule");
     if (o.graph_steps < 0 || (o.graph_steps > 0 && (o.graph_steps % 2 != 0 || o.graph_steps % o.residual_every != 0)))
         return fail(IFDLBM_EINVAL, "graph_steps must be 0, or even and a multiple of residual_every");
+    if (o.lambda_mode != IFDLBM_LAMBDA_LAGGED && o.lambda_mode != IFDLBM_LAMBDA_IMPLICIT)
+        return fail(IFDLBM_EINVAL, "unknown lambda_mode");
     if (o.segment_rows != 0 && (o.segment_rows < 16 || o.segment_rows > 4096))
         return fail(IFDLBM_EINVAL, "segment_rows must be 0 (automatic) or in [16, 4096]");
     for (int c = 0; c < n_cav; ++c) {
@@ -563,6 +567,7 @@ int ifdlbm_create(const ifdlbm_cavity* cav, int32_t n_cav, const ifdlbm_options*
         d.lam_newton = d.K / kCs2;
         d.lam0 = U / (v.re * kCs2);
         d.newtonian = v.n == 1.0;
+        d.implicit_lambda = o.lambda_mode == IFDLBM_LAMBDA_IMPLICIT;
         d.index = c;
         const int64_t nn = (int64_t)d.nx * d.ny;
         max_nodes = std::max(max_nodes, nn);
@@ -846,6 +851,8 @@ int ifdlbm_gradient(const ifdlbm_cavity* cav, const ifdlbm_options* opt, int64_t
     if (!cav || !opt || !J || !grad) return fail(IFDLBM_EINVAL, "null argument");
     if (objective != IFDLBM_OBJ_KINETIC_ENERGY) return fail(IFDLBM_EINVAL, "unknown objective");
     if (n_steps < 1) return fail(IFDLBM_EINVAL, "n_steps must be >= 1");
+    if (opt->lambda_mode != IFDLBM_LAMBDA_LAGGED)
+        return fail(IFDLBM_EINVAL, "the tangent-linear gradient follows the lagged lambda of Step (2)");
     const ifdlbm_cavity& v = *cav;
     if (v.n_xi < 5 || v.n_eta < 5 || (int64_t)v.n_xi * v.n_eta > (int64_t)1 << 26)
         return fail(IFDLBM_EINVAL, "n_xi, n_eta must be >= 5 and n_xi * n_eta <= 2^26");

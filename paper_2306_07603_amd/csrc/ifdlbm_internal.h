@@ -68,7 +68,7 @@ hipError_t launch_staged_step(int prec, const StepArgs& a, const NodeBlock* bloc
                               bool residual, hipStream_t s);
 
 // Fused schedule: one launch over the strip items [w0, w0 + nw).
-hipError_t launch_fused_step(int prec, const StepArgs& a, const StripItem* items, int w0, int nw,
+hipError_t launch_fused_step(int prec, bool implicit_lambda, const StepArgs& a, const StripItem* items, int w0, int nw,
                              bool residual, hipStream_t s);
 
 // Step (1) on every node of the listed blocks.

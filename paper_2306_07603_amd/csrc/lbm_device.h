@@ -91,6 +91,7 @@ struct CavityDesc {
     double dxi, deta;   // grid spacings of the computational square
     int32_t newtonian;  // n == 1 exactly
     int32_t index;      // cavity index in the handle
+    int32_t implicit_lambda;   // Step (2) solved for its own fixed point instead of lagged
 };
 
 // ---------------------------------------------------------------- storage
@@ -249,13 +250,51 @@ template <> __device__ __forceinline__ float pow_pos<float>(float x, float y)
 template <typename T>
 struct PowerLaw {
     T K3, expo, g2min, dt, lam_newton;
-    bool newtonian;
+    bool newtonian, implicit;
     __device__ __forceinline__ explicit PowerLaw(const CavityDesc& c)
         : K3(T(3) * T(c.K)), expo(T(c.expo)), g2min(T(c.g2min)), dt(T(c.dt)), lam_newton(T(c.lam_newton)),
-          newtonian(c.newtonian != 0)
+          newtonian(c.newtonian != 0), implicit(c.implicit_lambda != 0)
     {
     }
 };
+
+// Implicit Step (2): lambda = K3 max(18 Q / s^2, gamma_min^2)^expo with
+// s = 2 lambda + dt, Q = Pi:Pi.  h(lambda) = lambda - map(lambda) is negative
+// at 0 and crosses zero once below `hi` (for expo >= 0 the map falls from
+// map(0); for expo < 0 it rises, concave in s, up to the floor's value).
+// Newton steps h' = 1 + 4 expo map / s from the lagged value, replaced by
+// bisection of the bracket whenever a step leaves it or h' <= 0.
+template <typename V>
+__device__ __forceinline__ V implicit_relaxation_time(V Q18, V lam0, const PowerLaw<V>& pl)
+{
+    auto map = [&](V lam, bool& floored) {
+        const V s = V(2) * lam + pl.dt;
+        V g2 = Q18 / (s * s);
+        floored = !(g2 > pl.g2min);
+        g2 = floored ? pl.g2min : g2;
+        return pl.K3 * pow_pos<V>(g2, pl.expo);
+    };
+    bool fl;
+    V lo = V(0), hi = pl.expo >= V(0) ? map(V(0), fl) : pl.K3 * pow_pos<V>(pl.g2min, pl.expo);
+    V lam = lam0 > lo && lam0 < hi ? lam0 : V(0.5) * (lo + hi);
+    const V tol = sizeof(V) == 8 ? V(4e-16) : V(2e-7);
+    for (int it = 0; it < 60; ++it) {
+        const V m = map(lam, fl);
+        const V h = lam - m;
+        if (h < V(0))
+            lo = lam;
+        else
+            hi = lam;
+        const V s = V(2) * lam + pl.dt;
+        const V hp = V(1) + (fl ? V(0) : V(4) * pl.expo * m / s);
+        V next = hp > V(0) ? lam - h / hp : V(-1);
+        if (!(next > lo && next < hi)) next = V(0.5) * (lo + hi);
+        const V step = next > lam ? next - lam : lam - next;
+        lam = next;
+        if (step <= tol * lam || !(hi > lo)) break;
+    }
+    return lam;
+}
 
 template <typename T>
 __device__ __forceinline__ T relaxation_time(const T g[9], const T e[9], T lam_old, const PowerLaw<T>& pl)
@@ -281,8 +320,9 @@ __device__ __forceinline__ T relaxation_time(const T g[9], const T e[9], T lam_o
 }
 
 // Step (2) in the arithmetic V from d_k = e_k - g_k (T): Pi = -sum c c d, and
-// only its quadratic form enters gamma^2, so the sign drops out.
-template <typename T, typename V>
+// only its quadratic form enters gamma^2, so the sign drops out.  IMPLICIT
+// selects the fixed-point form (the cavity's implicit_lambda flag).
+template <bool IMPLICIT, typename T, typename V>
 __device__ __forceinline__ V relaxation_time_d(const T d[9], V lam_old, const PowerLaw<V>& pl)
 {
     if (pl.newtonian) return pl.lam_newton;
@@ -290,6 +330,7 @@ __device__ __forceinline__ V relaxation_time_d(const T d[9], V lam_old, const Po
     const V pxx = V((d[1] + d[3]) + s58);
     const V pyy = V((d[2] + d[4]) + s58);
     const V pxy = V((d[5] - d[6]) + (d[7] - d[8]));
+    if constexpr (IMPLICIT) return implicit_relaxation_time(V(18) * (pxx * pxx + V(2) * pxy * pxy + pyy * pyy), lam_old, pl);
     const V r = recip(V(2) * lam_old + pl.dt);
     V gamma2 = V(18) * (pxx * pxx + V(2) * pxy * pxy + pyy * pyy) * r * r;
     gamma2 = gamma2 > pl.g2min ? gamma2 : pl.g2min;

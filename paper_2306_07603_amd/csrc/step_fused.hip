@@ -44,13 +44,13 @@ constexpr int kRing = 5;                         // ring slots: rows t - 4 .. t
 #define IFD_FUSED_UNROLL_F32 5
 #endif
 #ifndef IFD_FUSED_UNROLL_F64
-#define IFD_FUSED_UNROLL_F64 1
+#define IFD_FUSED_UNROLL_F64 5
 #endif
 #ifndef IFD_FUSED_UNROLL_MIXED
 #define IFD_FUSED_UNROLL_MIXED 5
 #endif
 #ifndef IFD_FUSED_ONE_PATH
-#define IFD_FUSED_ONE_PATH 0   // 1: every wave takes the wall-aware code (half the code, a select per point)
+#define IFD_FUSED_ONE_PATH 1   // 1: every wave takes the wall-aware code (half the code, a select per point)
 #endif
 #ifndef IFD_FUSED_WAVES_F32
 #define IFD_FUSED_WAVES_F32 2
@@ -175,6 +175,14 @@ struct XiLane {
     }
 };
 
+// The workgroup is one wavefront, whose LDS instructions execute in program
+// order: a lane's read after another lane's write in the same wavefront sees
+// the write.  Ordering them needs only a compiler-level fence at wavefront
+// scope, which emits no s_barrier and no wait for outstanding memory
+// operations (a workgroup barrier would also drain the loads that fetch the
+// next row ahead of its use).
+__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
 template <typename T>
 __device__ __forceinline__ T lds_at(const T* row, uint32_t byte_offset)
 {
@@ -243,7 +251,7 @@ __device__ __forceinline__ void residual_add(const T (&gn)[9], const T (&old)[3]
 // One work item.  Register ring slot of row t - d at unrolled phase R:
 // (R + 5 - d) % 5 for f-bar+ and lambda (d = 0..4), (R + 10 - d) % 5 for
 // f(t + dt/2) (d = 2..6); with one row per trip R is 0 and the rings move.
-template <int PREC, bool RES, bool EDGE>
+template <int PREC, bool RES, bool EDGE, bool IMPL>
 struct March {
     using S = Storage<PREC>;
     using T = typename S::T;
@@ -373,7 +381,7 @@ struct March {
         auto& xs = sh.xs;
 #pragma unroll
         for (int k = 1; k < 9; ++k) xs[k - 1][lane + kPad] = ring[S2][k];
-        __syncthreads();
+        wave_sync();
         out[0] = base[0];
 #pragma unroll
         for (int k = 1; k < 9; ++k) {
@@ -404,7 +412,7 @@ struct March {
             if (moves_down(k)) o = o - my.apply(ring[S4][k], ring[S3][k], c0, ring[S1][k]);
             out[k] = o;
         }
-        __syncthreads();
+        wave_sync();
     }
 
     // Rows outside [1, ny-2] of a ring take the linear extrapolation 2 a1 - c0,
@@ -440,7 +448,7 @@ struct March {
             equilibrium(P, ux, uy, e);
 #pragma unroll
             for (int k = 0; k < 9; ++k) d[k] = e[k] - g[k];
-            const V l = relaxation_time_d(d, lam_old, pl);
+            const V l = relaxation_time_d<IMPL>(d, lam_old, pl);
             const Relax<V> rx(l, dtv);
             const T b_hat = T(rx.b_hat), b_bar = T(rx.b_bar);
 #pragma unroll
@@ -462,7 +470,7 @@ struct March {
                 transport<sg(R, 4), sg(R, 3), sg(R, 2), sg(R, 1), sg(R, 0)>(gbp, gbp[sg(R, 2)], mx, my, fb);
                 if (walls_b) {
                     publish(sh.wb, i, nx, fb);
-                    __syncthreads();
+                    wave_sync();
                     if (i == 0 || i == nx - 1) {
                         T src[9];
                         wall_source(sh.wb, i, nx, fb, src);
@@ -510,7 +518,7 @@ struct March {
             transport<sf(R, 6), sf(R, 5), sf(R, 4), sf(R, 3), sf(R, 2)>(fh, hp, mx, my, gn);
             if (walls_c) {
                 publish(sh.wc, i, nx, gn);
-                __syncthreads();
+                wave_sync();
                 if (i == 0 || i == nx - 1) {
                     T src[9];
                     wall_source(sh.wc, i, nx, gn, src);
@@ -607,7 +615,7 @@ struct March {
     }
 };
 
-template <int PREC, bool RES>
+template <int PREC, bool RES, bool IMPL>
 __global__ __launch_bounds__(kWaveLanes, Tuning<PREC>::kWaves) void k_fused(StepArgs a, const StripItem* items, int w0, int nw)
 {
     const int w = w0 + (int)blockIdx.x;
@@ -618,9 +626,9 @@ __global__ __launch_bounds__(kWaveLanes, Tuning<PREC>::kWaves) void k_fused(Step
     double acc[kPartials] = {0, 0, 0, 0, 0, 0, 0};
     // waves that hold column 1 or nx-2 take the first-order one-sided points (Eq. 2.7 at walls)
     if (IFD_FUSED_ONE_PATH || it.i0 <= 5 || it.i1 >= c.nx - 5)
-        March<PREC, RES, true>(a, it, c, sh, acc);
+        March<PREC, RES, true, IMPL>(a, it, c, sh, acc);
     else
-        March<PREC, RES, false>(a, it, c, sh, acc);
+        March<PREC, RES, false, IMPL>(a, it, c, sh, acc);
     if (RES) {
         // wavefront sum in a fixed order
 #pragma unroll
@@ -633,29 +641,38 @@ __global__ __launch_bounds__(kWaveLanes, Tuning<PREC>::kWaves) void k_fused(Step
     }
 }
 
-template <int PREC>
+template <int PREC, bool IMPL>
 hipError_t fused(const StepArgs& a, const StripItem* items, int w0, int nw, bool residual, hipStream_t s)
 {
     if (nw <= 0) return hipSuccess;
     if (residual)
-        hipLaunchKernelGGL((k_fused<PREC, true>), dim3(nw), dim3(kWaveLanes), 0, s, a, items, w0, nw);
+        hipLaunchKernelGGL((k_fused<PREC, true, IMPL>), dim3(nw), dim3(kWaveLanes), 0, s, a, items, w0, nw);
     else
-        hipLaunchKernelGGL((k_fused<PREC, false>), dim3(nw), dim3(kWaveLanes), 0, s, a, items, w0, nw);
+        hipLaunchKernelGGL((k_fused<PREC, false, IMPL>), dim3(nw), dim3(kWaveLanes), 0, s, a, items, w0, nw);
     return hipGetLastError();
+}
+
+template <bool IMPL>
+hipError_t fused_prec(int prec, const StepArgs& a, const StripItem* items, int w0, int nw, bool residual, hipStream_t s)
+{
+    switch (prec) {
+    case P_FP64: return fused<P_FP64, IMPL>(a, items, w0, nw, residual, s);
+    case P_FP32: return fused<P_FP32, IMPL>(a, items, w0, nw, residual, s);
+    case P_FP16DEV: return fused<P_FP16DEV, IMPL>(a, items, w0, nw, residual, s);
+    case P_FP32X: return fused<P_FP32X, IMPL>(a, items, w0, nw, residual, s);
+    case P_FP32SR: return fused<P_FP32SR, IMPL>(a, items, w0, nw, residual, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-hipError_t launch_fused_step(int prec, const StepArgs& a, const StripItem* items, int w0, int nw, bool residual, hipStream_t s)
+// implicit_lambda is a handle option: every cavity of a launch has the same flag
+hipError_t launch_fused_step(int prec, bool implicit_lambda, const StepArgs& a, const StripItem* items, int w0, int nw,
+                             bool residual, hipStream_t s)
 {
-    switch (prec) {
-    case P_FP64: return fused<P_FP64>(a, items, w0, nw, residual, s);
-    case P_FP32: return fused<P_FP32>(a, items, w0, nw, residual, s);
-    case P_FP16DEV: return fused<P_FP16DEV>(a, items, w0, nw, residual, s);
-    case P_FP32X: return fused<P_FP32X>(a, items, w0, nw, residual, s);
-    case P_FP32SR: return fused<P_FP32SR>(a, items, w0, nw, residual, s);
-    }
-    return hipErrorInvalidValue;
+    return implicit_lambda ? fused_prec<true>(prec, a, items, w0, nw, residual, s)
+                           : fused_prec<false>(prec, a, items, w0, nw, residual, s);
 }
 
 }  // namespace ifd

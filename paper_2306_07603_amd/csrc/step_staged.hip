@@ -82,7 +82,9 @@ __global__ __launch_bounds__(kNodeBlock) void k_stage_a(StepArgs a, const NodeBl
     equilibrium(P, ux, uy, e);
 #pragma unroll
     for (int k = 0; k < 9; ++k) d[k] = e[k] - g[k];
-    const V lam = relaxation_time_d(d, V(l[c.l_off + r.id]), PowerLaw<V>(c));
+    const PowerLaw<V> pl(c);
+    const V lam = pl.implicit ? relaxation_time_d<true>(d, V(l[c.l_off + r.id]), pl)
+                              : relaxation_time_d<false>(d, V(l[c.l_off + r.id]), pl);
     const Relax<V> rx(lam, V(c.dt));
     const T b_hat = T(rx.b_hat), b_bar = T(rx.b_bar);
     T* hp = static_cast<T*>(a.hat_plus);

@@ -54,7 +54,8 @@ class ifdlbm_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("cfl", ctypes.c_double), ("mix", ctypes.c_double),
                 ("rho0", ctypes.c_double), ("gamma_min", ctypes.c_double), ("residual_every", ctypes.c_int32),
                 ("kernel", ctypes.c_int32), ("batched", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
-                ("dt_rule", ctypes.c_int32), ("segment_rows", ctypes.c_int32), ("hip_stream", ctypes.c_void_p)]
+                ("dt_rule", ctypes.c_int32), ("segment_rows", ctypes.c_int32), ("lambda_mode", ctypes.c_int32),
+                ("hip_stream", ctypes.c_void_p)]
 
 
 class ifdlbm_info_t(ctypes.Structure):
@@ -68,6 +69,9 @@ class ifdlbm_regime_t(ctypes.Structure):
                 ("f_main", ctypes.c_double), ("f_second", ctypes.c_double), ("harmonic_fraction", ctypes.c_double),
                 ("second_fraction", ctypes.c_double)]
 
+
+IFDLBM_LAMBDA_LAGGED = 0
+IFDLBM_LAMBDA_IMPLICIT = 1
 
 IFDLBM_REGIME_STEADY = 0
 IFDLBM_REGIME_PERIODIC = 1

@@ -1,0 +1,253 @@
+"""Parameter studies of arXiv:2306.07603 run through the library.
+
+python -m paper_2306_07603_amd.studies <name> [--out FILE] [options]
+
+  regime     Section 6.3: the flow regime (steady / periodic / quasi-periodic /
+             aperiodic) of the cavities whose regime the paper reports, from the
+             centre velocity and the kinetic energy of Eq. (5.1) recorded on the
+             device, classified by the library's spectral classifier.
+  precision  the 257 x 257 precision sweep: steady states in FP64, and the FP32
+             storage modes run as many steps, velocity error against FP64.
+  lag        Step (2) with the lagged lambda of Section 3 against its implicit
+             fixed point: transient difference and steady states.
+  stress     a high-Reynolds stability check (theta = 45 deg, Re = 50 000).
+  unsteady   the 1025 x 1025 unsteady case in FP16-deviation, FP32 and FP64
+             storage: time-averaged |u| differences and throughput.
+
+Every study prints one progress line per chunk of steps and writes a JSON
+summary.  Inputs are the paper's problem statement with seeded parameters; no
+dataset is read.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import ifdlbm as M
+
+# (theta, n, Re, regime the paper reports) -- Section 6.3, 256 x 256 grids
+PAPER_REGIMES = [
+    (60.0, 1.5, 3000.0, "steady"), (60.0, 1.5, 4000.0, "periodic"), (60.0, 1.5, 5000.0, "periodic"),
+    (60.0, 1.0, 2000.0, "steady"), (60.0, 1.0, 2500.0, "periodic"), (60.0, 1.0, 3000.0, "quasi-periodic"),
+    (60.0, 1.0, 4000.0, "turbulent"), (60.0, 0.5, 1000.0, "periodic"), (60.0, 0.5, 2000.0, "periodic"),
+    (75.0, 1.5, 5000.0, "steady"), (75.0, 1.5, 6000.0, "periodic"),
+    (45.0, 1.5, 6000.0, "quasi-periodic"), (45.0, 1.5, 7000.0, "periodic"),
+]
+
+
+def log(msg: str) -> None:
+    print("[study] " + msg, flush=True)
+
+
+def to_steady(h, tol: float, max_steps: int, chunk: int = 100000, label: str = ""):
+    """ifdlbm_run_to_steady in chunks, with a progress line per chunk: returns
+    (all converged, steps per cavity, E(u), E(P))."""
+    total = None
+    t0 = time.time()
+    done = 0
+    while True:
+        rc, steps, ru, rp = M.ifdlbm_run_to_steady(h, tol, min(chunk, max_steps - done))
+        total = steps.copy() if total is None else total + steps
+        done += min(chunk, max_steps - done)
+        log("%s: %d steps, E(u) max %.2e, %.0f s" % (label, done, np.nanmax(ru), time.time() - t0))
+        if rc == M.IFDLBM_OK or done >= max_steps:
+            return rc == M.IFDLBM_OK, total, ru, rp
+
+
+def regime(n_side: int = 257, time_units: float = 3000.0, every: int = 50, precision: str = "fp32sr",
+           chunk: int = 100000, steady_tol: float = 1e-4) -> dict:
+    """Run every case of PAPER_REGIMES for `time_units` (lid speed 0.1, height
+    1), record every `every` steps, classify the second half of the record."""
+    cav = [M.Cavity(n_side, n_side, re, n, th, 0.1) for th, n, re, _ in PAPER_REGIMES]
+    o = M.ifdlbm_default_options(precision=precision, residual_every=1000, graph_steps=1000)
+    h = M.ifdlbm_create(cav, o)
+    dts = [M.ifdlbm_time_step(h, c) for c in range(len(cav))]
+    steps = int(time_units / min(dts))
+    cap = steps // every + 2
+    M.ifdlbm_record(h, every, cap)
+    t0 = time.time()
+    done = 0
+    while done < steps:
+        k = min(chunk, steps - done)
+        k = max(1000, k // 1000 * 1000)
+        M.ifdlbm_step(h, k)
+        M.ifdlbm_sync(h)
+        done += k
+        log("regime: %d / %d steps, %.0f s" % (done, steps, time.time() - t0))
+    out = []
+    for c, (th, n, re, paper) in enumerate(PAPER_REGIMES):
+        st, u, v, ke = M.ifdlbm_get_record(h, c, cap)
+        half = st.size // 2
+        dt_sample = every * dts[c]
+        rk = M.ifdlbm_classify(ke[half:], dt_sample, steady_tol) if np.all(np.isfinite(ke[half:])) else None
+        ru = M.ifdlbm_classify(u[half:], dt_sample, steady_tol) if np.all(np.isfinite(u[half:])) else None
+        out.append({"theta": th, "n": n, "re": re, "paper": paper, "status": M.ifdlbm_status(h, c),
+                    "time_units": float(st[-1] * dts[c]) if st.size else 0.0,
+                    "ke": rk, "u_centre": ru, "u_last": float(u[-1]) if u.size else None,
+                    "v_last": float(v[-1]) if v.size else None})
+        log("theta %g n %.1f Re %g: paper %s, ke %s (f %.4g), u %s (f %.4g)"
+            % (th, n, re, paper, rk["name"] if rk else "non-finite", rk["f_main"] if rk else 0,
+               ru["name"] if ru else "non-finite", ru["f_main"] if ru else 0))
+    return {"study": "regime", "n_side": n_side, "time_units": time_units, "every": every, "precision": precision,
+            "steady_tol": steady_tol, "steps": steps, "seconds": time.time() - t0, "cases": out}
+
+
+def precision(n_side: int = 257, tol: float = 1e-8, max_steps: int = 2000000) -> dict:
+    """Steady states of Re = 1000, n in {0.5, 1, 1.5} x theta in {45, 60, 90}
+    in FP64 to E(u), E(P) <= tol, then the FP32 storage modes for as many steps."""
+    specs = [(th, n) for n in (0.5, 1.0, 1.5) for th in (45.0, 60.0, 90.0)]
+    cav = [M.Cavity(n_side, n_side, 1000.0, n, th, 0.1) for th, n in specs]
+    t0 = time.time()
+    h64 = M.ifdlbm_create(cav, M.ifdlbm_default_options(precision="fp64", residual_every=1000, graph_steps=1000))
+    ok, steps, ru, rp = to_steady(h64, tol, max_steps, label="precision fp64")
+    log("fp64: converged %s, steps %s, %.0f s" % (ok, list(steps), time.time() - t0))
+    ref = [M.ifdlbm_get_fields(h64, c) for c in range(len(cav))]
+    stat = [M.ifdlbm_status(h64, c) for c in range(len(cav))]
+    res = {"study": "precision", "n_side": n_side, "tol": tol, "cases": []}
+    errs = {}
+    for prec in ("fp32sr", "fp32", "fp32x", "fp16dev"):
+        h = M.ifdlbm_create(cav, M.ifdlbm_default_options(precision=prec, residual_every=1000, graph_steps=1000))
+        e = []
+        # every cavity runs as many steps as its FP64 run took: step the batch to the largest count and read
+        # each cavity when its count is reached
+        order = np.argsort(steps)
+        done = 0
+        for c in order:
+            M.ifdlbm_step(h, int(steps[c]) - done)
+            done = int(steps[c])
+            u, v, _ = M.ifdlbm_get_fields(h, int(c))
+            scale = max(np.abs(ref[c][0]).max(), np.abs(ref[c][1]).max())
+            e.append((int(c), float(max(np.abs(u - ref[c][0]).max(), np.abs(v - ref[c][1]).max()) / scale)))
+        errs[prec] = dict(e)
+        log("%s: %s, %.0f s" % (prec, ["%.1e" % errs[prec][c] for c in range(len(cav))], time.time() - t0))
+    for c, (th, n) in enumerate(specs):
+        res["cases"].append({"theta": th, "n": n, "re": 1000.0, "fp64_status": stat[c], "steps": int(steps[c]),
+                             "res_u": float(ru[c]), "res_p": float(rp[c]),
+                             "vel_error": {p: errs[p][c] for p in errs}})
+    res["seconds"] = time.time() - t0
+    return res
+
+
+def lag(n_side: int = 129) -> dict:
+    """Lagged against implicit lambda (Step 2): the velocity difference after
+    a few time units, and at steady state."""
+    specs = [(60.0, 0.5, 100.0), (60.0, 1.5, 100.0), (45.0, 0.75, 400.0)]
+    cav = [M.Cavity(n_side, n_side, re, n, th, 0.1) for th, n, re in specs]
+    out = {"study": "lag", "n_side": n_side, "cases": []}
+    hl = M.ifdlbm_create(cav, M.ifdlbm_default_options(precision="fp64", residual_every=500, graph_steps=1000))
+    hi = M.ifdlbm_create(cav, M.ifdlbm_default_options(precision="fp64", residual_every=500, graph_steps=1000,
+                                                       lambda_mode=M.IFDLBM_LAMBDA_IMPLICIT))
+    marks = []
+    for n in (10, 100, 1000, 10000):
+        M.ifdlbm_step(hl, n - (marks[-1] if marks else 0))
+        M.ifdlbm_step(hi, n - (marks[-1] if marks else 0))
+        marks.append(n)
+        row = []
+        for c in range(len(cav)):
+            ul, vl, _ = M.ifdlbm_get_fields(hl, c)
+            ui, vi, _ = M.ifdlbm_get_fields(hi, c)
+            scale = max(np.abs(ul).max(), np.abs(vl).max())
+            row.append(float(max(np.abs(ul - ui).max(), np.abs(vl - vi).max()) / scale))
+        log("lag: step %d, relative velocity difference %s" % (n, ["%.2e" % x for x in row]))
+        out.setdefault("transient", []).append({"step": n, "diff": row})
+    rl = to_steady(hl, 1e-10, 3000000, label="lag lagged")
+    ri = to_steady(hi, 1e-10, 3000000, label="lag implicit")
+    for c, (th, n, re) in enumerate(specs):
+        ul, vl, _ = M.ifdlbm_get_fields(hl, c)
+        ui, vi, _ = M.ifdlbm_get_fields(hi, c)
+        scale = max(np.abs(ul).max(), np.abs(vl).max())
+        d = float(max(np.abs(ul - ui).max(), np.abs(vl - vi).max()) / scale)
+        out["cases"].append({"theta": th, "n": n, "re": re, "steps_lagged": int(rl[1][c]),
+                             "steps_implicit": int(ri[1][c]), "steady_diff": d})
+        log("lag: theta %g n %g Re %g steady after %d / %d steps, difference %.2e"
+            % (th, n, re, rl[1][c], ri[1][c], d))
+    return out
+
+
+def stress(n_side: int = 129, time_units: float = 500.0) -> dict:
+    """theta = 45 deg, Re = 50 000 on 129 x 129 (Newtonian and two power
+    laws): does the run stay finite?"""
+    specs = [(45.0, 1.0, 50000.0), (45.0, 0.8, 50000.0), (45.0, 1.2, 50000.0)]
+    cav = [M.Cavity(n_side, n_side, re, n, th, 0.1) for th, n, re in specs]
+    h = M.ifdlbm_create(cav, M.ifdlbm_default_options(precision="fp64", residual_every=1000, graph_steps=1000))
+    steps = int(time_units / min(M.ifdlbm_time_step(h, c) for c in range(len(cav)))) // 1000 * 1000
+    t0 = time.time()
+    for k in range(0, steps, 100000):
+        M.ifdlbm_step(h, min(100000, steps - k))
+        M.ifdlbm_sync(h)
+        log("stress: %d / %d steps, %.0f s" % (min(k + 100000, steps), steps, time.time() - t0))
+    res = M.ifdlbm_get_residuals(h)
+    out = {"study": "stress", "n_side": n_side, "steps": steps, "cases": []}
+    for c, (th, n, re) in enumerate(specs):
+        u, v, _ = M.ifdlbm_get_fields(h, c)
+        finite = bool(np.all(np.isfinite(u)) and np.all(np.isfinite(v)))
+        out["cases"].append({"theta": th, "n": n, "re": re, "finite": finite, "status": M.ifdlbm_status(h, c),
+                             "res_u": float(res[0][c]), "max_speed": float(np.hypot(u, v).max()) if finite else None})
+        log("stress: theta %g n %g Re %g finite %s" % (th, n, re, finite))
+    return out
+
+
+def unsteady(n_side: int = 1025, steps: int = 200000, average_from: int = 100000, every: int = 1000) -> dict:
+    """theta = 75 deg, n = 1.2, Re = 1e4 on 1025 x 1025 in FP16-deviation, FP32
+    (stochastic rounding) and FP64 storage: time average of |u| over steps
+    [average_from, steps) sampled every `every` steps, and throughput."""
+    cav = [M.Cavity(n_side, n_side, 1e4, 1.2, 75.0, 0.1)]
+    out = {"study": "unsteady", "n_side": n_side, "steps": steps, "average_from": average_from, "every": every,
+           "runs": {}}
+    means = {}
+    for prec in ("fp16dev", "fp32sr", "fp64"):
+        h = M.ifdlbm_create(cav, M.ifdlbm_default_options(precision=prec, residual_every=1000, graph_steps=1000))
+        t0 = time.time()
+        acc, nacc = None, 0
+        done = 0
+        while done < steps:
+            M.ifdlbm_step(h, every)
+            done += every
+            if done > average_from:
+                u, v, _ = M.ifdlbm_get_fields(h, 0)
+                s = np.hypot(u, v)
+                acc = s if acc is None else acc + s
+                nacc += 1
+            if done % 20000 == 0:
+                log("unsteady %s: %d / %d steps, %.0f s" % (prec, done, steps, time.time() - t0))
+        M.ifdlbm_sync(h)
+        wall = time.time() - t0
+        means[prec] = acc / nacc
+        out["runs"][prec] = {"seconds": wall, "samples": nacc,
+                             "mlups_with_sampling": n_side * n_side * steps / wall / 1e6}
+        h.close()
+    ref = means["fp64"]
+    for prec in ("fp16dev", "fp32sr"):
+        out["runs"][prec]["mean_speed_rel_diff_vs_fp64"] = float(np.abs(means[prec] - ref).max() / ref.max())
+        log("unsteady %s: time-averaged |u| max relative difference to FP64 %.2e"
+            % (prec, out["runs"][prec]["mean_speed_rel_diff_vs_fp64"]))
+    return out
+
+
+STUDIES = {"regime": regime, "precision": precision, "lag": lag, "stress": stress, "unsteady": unsteady}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("name", choices=sorted(STUDIES))
+    ap.add_argument("--out", default="")
+    ap.add_argument("--time-units", type=float, default=None, help="regime / stress: simulated time")
+    args = ap.parse_args(argv)
+    kw = {}
+    if args.time_units is not None and args.name in ("regime", "stress"):
+        kw["time_units"] = args.time_units
+    res = STUDIES[args.name](**kw)
+    text = json.dumps(res, indent=1, default=float)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(text)
+    print(text[:2000])
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -175,6 +175,56 @@ def check_relaxation_time_power_law():
         assert abs(got - 1e-3 * (1e-6) ** ((n - 1) / 2) / cs2) < 1e-12 * got
 
 
+def check_implicit_lambda():
+    """Implicit Step (2) (reading R20): (a) for a node whose f carries the
+    non-equilibrium part of a strain rate S at the power-law lambda of S
+    itself, the implicit lambda is that lambda (closed form, Eqs. 1.4, 2.12,
+    2.14, 2.18); (b) on arbitrary nodes it is a fixed point of the lagged
+    Step (2), an independent code path; (c) Newtonian: K / c_s^2 exactly."""
+    _, _, _, _, cs2 = O.lattice()
+    rng = _rng(17)
+    for n in (0.5, 0.8, 1.3, 1.5):
+        for _ in range(10):
+            feq, _ = _random_node(rng)
+            a, b = rng.normal(0, 0.05), rng.normal(0, 0.05)
+            S = np.array([[2 * a, b], [b, -2 * a]])
+            dt, K = rng.uniform(1e-3, 0.05), rng.uniform(1e-4, 1e-2)
+            lam = K * (0.5 * (S * S).sum()) ** ((n - 1) / 2) / cs2
+            f = feq + _nonequilibrium(-lam * cs2 * S)
+            fhat = f + dt / (2 * lam) * (f - feq)
+            got = O.relaxation_time_implicit(fhat, feq, dt, K, n, 1e-9)
+            assert abs(got - lam) <= 1e-12 * lam, (n, got, lam)
+            # arbitrary node: f-hat with a random non-equilibrium part
+            fh = feq + rng.normal(0, 1e-3, 9)
+            li = O.relaxation_time_implicit(fh, feq, dt, K, n, 1e-9)
+            back = O.relaxation_time(fh, feq, li, dt, K, n, 1e-9)
+            assert abs(back - li) <= 1e-12 * li, (n, back, li)
+    feq, _ = _random_node(rng)
+    fh = feq + rng.normal(0, 1e-3, 9)
+    assert O.relaxation_time_implicit(fh, feq, 0.01, 2e-3, 1.0, 1e-6) == 2e-3 / cs2
+
+
+def check_implicit_steady_state_equals_lagged():
+    """At a steady state the lag of Step (2) vanishes (lambda_old = lambda):
+    lagged and implicit runs of a slow power-law cavity reach the same state,
+    while their transients differ."""
+    base = dict(nx=17, ny=17, re=1.0, n=0.7, theta_deg=60.0, rho0=0.0)
+    pl, pi = O.Params(**base), O.Params(**base, lambda_mode=O.LAMBDA_IMPLICIT)
+    Fl, Ll = O.init(pl)
+    Fi, Li = O.init(pi)
+    O.run(pl, Fl, Ll, 40)
+    O.run(pi, Fi, Li, 40)
+    ul, ui = O.fields(pl, Fl)[0], O.fields(pi, Fi)[0]
+    assert np.abs(ul - ui).max() > 1e-6 * np.abs(ul).max()
+    O.run(pl, Fl, Ll, 3960)
+    O.run(pi, Fi, Li, 3960)
+    rl = O.run(pl, Fl, Ll, 1)
+    O.run(pi, Fi, Li, 1)
+    assert rl[0] < 1e-12, rl
+    ul, ui = O.fields(pl, Fl)[0], O.fields(pi, Fi)[0]
+    assert np.abs(ul - ui).max() <= 1e-9 * np.abs(ul).max()
+
+
 # ---------------------------------------------------------------- geometry
 
 def check_geometry_matches_paper():
@@ -510,6 +560,8 @@ ALL_CHECKS = [
     check_conversions_follow_definitions,
     check_collision_invariants,
     check_relaxation_time_power_law,
+    check_implicit_lambda,
+    check_implicit_steady_state_equals_lagged,
     check_geometry_matches_paper,
     check_metric_exact_on_linear_fields,
     check_stencils_on_quartics,

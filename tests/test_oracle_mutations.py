@@ -45,6 +45,10 @@ MUTATIONS = [
      [C.check_lattice_matches_paper]),
     ("energy_edge_weights", "? 0.5 : 1.0;\n            double wj", "? 1.0 : 1.0;\n            double wj",
      [C.check_kinetic_energy_weights]),
+    ("implicit_strain_scale", "double s = 2.0 * lam + dt;", "double s = lam + dt;",
+     [C.check_implicit_lambda]),
+    ("implicit_bracket_direction", "            lo = mid;\n        else", "            hi = mid;\n        else",
+     [C.check_implicit_lambda]),
     ("viscosity_from_consistency", "return mu / CS2;", "return mu * CS2;",
      [C.check_relaxation_time_power_law, C.check_taylor_green_decay]),
 ]
