@@ -32,6 +32,7 @@ WORKLOAD = ("256-cavity uneven batch: sides {65,129,257,513}, Re log-uniform [10
             "one launch per step, HIP-graph replay")
 # storage of the distributions and arithmetic type of each precision mode
 PRECISION = {
+    "fp32srf": ("FP32, stochastic rounding of an FP64 final update", "f32"),
     "fp32sr": ("FP32, stochastic rounding", "f64"),
     "fp32": ("FP32, round to nearest", "f32"),
     "fp32x": ("FP32, round to nearest", "f64"),
@@ -42,6 +43,41 @@ PRECISION = {
 
 def log(msg: str) -> None:
     print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+# Kernel sources whose content the measured traffic belongs to: the traffic
+# record in profiles/ is used only while these files are unchanged.
+KERNEL_SOURCES = ["paper_2306_07603_amd/csrc/step_fused.hip", "paper_2306_07603_amd/csrc/lbm_device.h",
+                  "paper_2306_07603_amd/csrc/ifdlbm_internal.h"]
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_fused_traffic_batch256.txt")
+
+
+def kernel_source_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(precision: str):
+    """HBM bytes per launch of the step kernel from the rocprofv3 FETCH_SIZE and
+    WRITE_SIZE passes recorded in profiles/ (each scaled by the same counter's
+    reading for a plain copy of known size), or None when the record is absent
+    or was taken on other kernel sources."""
+    if not os.path.exists(TRAFFIC_RECORD):
+        return None
+    rec = {}
+    with open(TRAFFIC_RECORD) as f:
+        for line in f:
+            if ":" in line and not line.startswith(" "):
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip()
+    if rec.get("kernel_sources_sha256") != kernel_source_digest():
+        return None
+    key = "bytes_per_launch_" + precision
+    return float(rec[key]) if key in rec else None
 
 
 def time_steps(M, h, stream, steps: int, warmup: int):
@@ -101,10 +137,12 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--kernel", default="fused", choices=["fused", "staged"])
-    ap.add_argument("--precision", default="fp32sr", choices=["fp32sr", "fp32", "fp32x", "fp16dev", "fp64"])
+    ap.add_argument("--precision", default="fp32sr", choices=["fp32srf", "fp32sr", "fp32", "fp32x", "fp16dev", "fp64"])
     ap.add_argument("--residual-every", type=int, default=100)
     ap.add_argument("--graph-steps", type=int, default=100)
     ap.add_argument("--plain-steps", type=int, default=100, help="steps of the plain FP64 comparison run (0: skip)")
+    ap.add_argument("--other-steps", type=int, default=300,
+                    help="steps of each other FP32-storage mode, reported beside the headline (0: skip)")
     ap.add_argument("--cpu-steps", type=int, default=100, help="steps of the CPU oracle sample (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy three times (scale for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -161,6 +199,20 @@ def main() -> int:
         log("fp64 plain: %.1f MLUPS" % mlups64)
         h64.close()
 
+    other = {}
+    if args.other_steps > 0:
+        for prec in ("fp32srf", "fp32sr", "fp32"):
+            if prec == args.precision:
+                continue
+            o2 = M.ifdlbm_default_options(precision=prec, kernel=args.kernel, residual_every=args.residual_every,
+                                          graph_steps=args.graph_steps, batched=1, hip_stream=stream.cuda_stream)
+            h2 = M.ifdlbm_create(cav, o2)
+            w2, e2 = time_steps(M, h2, stream, args.other_steps, min(args.warmup, 50))
+            other[prec] = {"value": nodes * args.other_steps / w2 / 1e6, "unit": "MLUPS",
+                           "storage": PRECISION[prec][0], "dtype": PRECISION[prec][1], "steps": args.other_steps}
+            log("%s batched: %.1f MLUPS" % (prec, other[prec]["value"]))
+            h2.close()
+
     cpu = cpu_baseline(specs, args.cpu_steps) if args.cpu_steps > 0 else None
     if cpu:
         log("cpu oracle: %.3f MLUPS" % cpu["value"])
@@ -174,10 +226,11 @@ def main() -> int:
                    "diverged_cavities": diverged,
                    "residual_every": args.residual_every, "graph_steps": args.graph_steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.precision),
                      "kernel_ms": kernel_ms, "alg_bytes_per_launch": alg_bytes,
                      "alg_bytes_per_node": info["alg_bytes_per_node"]},
         "fp64_plain": plain,
+        "other_fp32_storage_modes": other or None,
         "speedup_vs_fp64_plain": (mlups / plain["value"]) if plain else None,
         "cpu_baseline": cpu,
     }

@@ -56,8 +56,13 @@ typedef struct ifdlbm_s ifdlbm_t;
 #define IFDLBM_FP16DEV  2   /* FP16 scaled deviations (f-hat - omega_k rho0)/omega_k, FP32 lambda
                                and FP32 arithmetic                                                 */
 #define IFDLBM_FP32X    3   /* FP32 deviations and lambda in memory, FP64 arithmetic               */
-#define IFDLBM_FP32SR   4   /* as FP32X, the deviations stored with stochastic rounding (unbiased:
-                               no constant forcing of a steady state by the rounding)             */
+#define IFDLBM_FP32SR   4   /* FP32 deviations stored with stochastic rounding (unbiased: no constant
+                               forcing of a steady state by the rounding), FP64 arithmetic of the
+                               distributions, FP32 arithmetic of Step (2)                          */
+#define IFDLBM_FP32SRF  5   /* FP32 deviations stored with stochastic rounding, FP32 arithmetic
+                               except the final update of each stored value: f-hat+ is rebuilt in
+                               FP64 from the stored f-hat and the FP32 streaming increment added
+                               in FP64 before the rounding                                         */
 
 /* kernel schedule (options.kernel) */
 #define IFDLBM_KERNEL_FUSED    0   /* one fused launch per step (default)                        */
@@ -92,7 +97,7 @@ typedef struct {
 } ifdlbm_cavity;
 
 typedef struct {
-    int32_t precision;      /* IFDLBM_FP64 | _FP32 | _FP16DEV | _FP32X | _FP32SR                       */
+    int32_t precision;      /* IFDLBM_FP64 | _FP32 | _FP16DEV | _FP32X | _FP32SR | _FP32SRF            */
     double  cfl;            /* Courant number, > 0 (paper: 0.5); dt follows dt_rule                   */
     double  mix;            /* weight of the central scheme in Eq. (2.5), [0, 1] (default 0.5)       */
     double  rho0;           /* constant density of Eq. (2.8) (default 1); u and P do not depend on it */
@@ -172,6 +177,15 @@ int ifdlbm_set_state(ifdlbm_t* h, int32_t cav, const double* fhat, const double*
 /* IFDLBM_STATUS_* of cavity cav, or a negative error code. */
 int ifdlbm_status(ifdlbm_t* h, int32_t cav);
 
+/* Tile-shape autotuner of the fused kernel: times steps_per_trial steps (after one warm-up step) of the
+   handle's running cavities for every candidate row-segment length (16 ... 128 rows), keeps the fastest in
+   options.segment_rows, and restores the state, step count, residual sums and random-word counter, so later results are those
+   without the call (they do not depend on the segmentation).  *segment_rows and *ms_per_step (either may be
+   NULL) receive the choice and its time per step; 0 for the staged schedule, which has no tile shape.  Device
+   memory for one copy of the state is allocated and freed inside the call, which synchronises the stream.
+   Errors: EINVAL (steps_per_trial outside [1, 10000]), ENOMEM, EDEVICE. */
+int ifdlbm_autotune(ifdlbm_t* h, int32_t steps_per_trial, int32_t* segment_rows, double* ms_per_step);
+
 /* Work sizes of the handle (see ifdlbm_info_t). */
 int ifdlbm_info(ifdlbm_t* h, ifdlbm_info_t* info);
 
@@ -189,6 +203,18 @@ int ifdlbm_info(ifdlbm_t* h, ifdlbm_info_t* info);
    J and grad are caller-owned.  Errors: EINVAL, ENOMEM, EDEVICE. */
 int ifdlbm_gradient(const ifdlbm_cavity* cav, const ifdlbm_options* opt, int64_t n_steps, int32_t objective,
                     double* J, double grad[3]);
+
+/* The same J and grad[3] (dJ/dtheta [rad], dJ/dn, dJ/du_lid) by the discrete adjoint: a forward sweep of n_steps
+   steps of the handle's own step kernel (options precision, kernel, segment_rows, cfl, mix, rho0, gamma_min,
+   dt_rule and hip_stream apply; lambda_mode must be LAGGED) keeps the state every checkpoint_every steps; the
+   reverse sweep recomputes each segment from its checkpoint and walks it backwards through the transposed
+   Steps (2)-(6) of Section 4 in FP64, accumulating the parameter adjoints in FP64.  With an FP32 storage mode
+   the gradient is that of the FP64 step linearised about the FP32 trajectory.  Device memory: the raw state
+   once per checkpoint, (min(checkpoint_every, n_steps) + 1) FP64 states of 10 doubles per node, and about
+   60 doubles per node of work arrays, allocated and freed inside the call, which synchronises the stream.
+   Errors: EINVAL, ENOMEM, EDEVICE, EDIVERGED (non-finite trajectory or adjoint). */
+int ifdlbm_adjoint(const ifdlbm_cavity* cav, const ifdlbm_options* opt, int64_t n_steps, int32_t checkpoint_every,
+                   int32_t objective, double* J, double grad[3]);
 
 /* Probe record for the flow-regime study of Section 6.2.  every >= 1: after each step whose count (steps
    since creation) is a multiple of `every`, append to the record of every cavity the velocity (u, v) at the

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libifdlbm.so")
-SOURCES = ["api.hip", "kernels_common.hip", "step_staged.hip", "step_fused.hip", "gradient.hip", "regime.cpp"]
+SOURCES = ["api.hip", "kernels_common.hip", "step_staged.hip", "step_fused.hip", "gradient.hip", "adjoint.hip", "regime.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

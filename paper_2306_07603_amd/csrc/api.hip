@@ -478,7 +478,7 @@ int ifdlbm_create(const ifdlbm_cavity* cav, int32_t n_cav, const ifdlbm_options*
     *out = nullptr;
     if (!cav || !opt || n_cav <= 0) return fail(IFDLBM_EINVAL, "need at least one cavity and options");
     const ifdlbm_options& o = *opt;
-    if (o.precision < IFDLBM_FP64 || o.precision > IFDLBM_FP32SR) return fail(IFDLBM_EINVAL, "unknown precision");
+    if (o.precision < IFDLBM_FP64 || o.precision > IFDLBM_FP32SRF) return fail(IFDLBM_EINVAL, "unknown precision");
     if (!(o.cfl > 0.0) || !(o.mix >= 0.0 && o.mix <= 1.0) || !(o.gamma_min > 0.0) || !std::isfinite(o.rho0))
         return fail(IFDLBM_EINVAL, "cfl must be > 0, mix in [0, 1], gamma_min > 0, rho0 finite");
     if (o.residual_every < 1) return fail(IFDLBM_EINVAL, "residual_every must be >= 1");
@@ -825,6 +825,85 @@ int ifdlbm_status(ifdlbm_t* h, int32_t cav)
     return h->status[cav];
 }
 
+int ifdlbm_autotune(ifdlbm_t* h, int32_t steps_per_trial, int32_t* segment_rows, double* ms_per_step)
+{
+    if (!h) return fail(IFDLBM_EINVAL, "null handle");
+    if (steps_per_trial < 1 || steps_per_trial > 10000) return fail(IFDLBM_EINVAL, "steps_per_trial must be in [1, 10000]");
+    if (segment_rows) *segment_rows = 0;
+    if (ms_per_step) *ms_per_step = 0.0;
+    if (h->opt.kernel != IFDLBM_KERNEL_FUSED) return IFDLBM_OK;   // the staged schedule has no tile shape
+    // every trial starts from the current state, which is restored at the end
+    const int prec = h->opt.precision;
+    const size_t fb = h->f_elems * f_elem_size(prec), lb = h->l_elems * l_elem_size(prec);
+    const size_t rb = (size_t)h->n_cav * kPartials * sizeof(double);
+    void *bf = nullptr, *bl = nullptr, *br = nullptr;
+    uint32_t* bs = nullptr;
+    int rc = dalloc(&bf, fb);
+    if (!rc) rc = dalloc(&bl, lb);
+    if (!rc) rc = dalloc(&br, rb);
+    if (!rc) rc = dalloc(&bs, sizeof(uint32_t));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        rc = fail(IFDLBM_EDEVICE, "hipEventCreate");
+    const int cur0 = h->cur;
+    const int64_t count0 = h->step_count;
+    const int32_t rows0 = h->opt.segment_rows;
+    auto save = [&]() {
+        hipError_t e = hipMemcpyAsync(bf, h->d_f[cur0], fb, hipMemcpyDeviceToDevice, h->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(bl, h->d_l[cur0], lb, hipMemcpyDeviceToDevice, h->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(br, h->d_res, rb, hipMemcpyDeviceToDevice, h->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(bs, h->d_seed, sizeof(uint32_t), hipMemcpyDeviceToDevice, h->stream);
+        return e;
+    };
+    auto restore = [&]() {
+        hipError_t e = hipMemcpyAsync(h->d_f[cur0], bf, fb, hipMemcpyDeviceToDevice, h->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(h->d_l[cur0], bl, lb, hipMemcpyDeviceToDevice, h->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(h->d_res, br, rb, hipMemcpyDeviceToDevice, h->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(h->d_seed, bs, sizeof(uint32_t), hipMemcpyDeviceToDevice, h->stream);
+        h->cur = cur0;
+        h->step_count = count0;
+        return e;
+    };
+    if (!rc && save() != hipSuccess) rc = fail(IFDLBM_EDEVICE, "autotune: state backup");
+    int best = 0;
+    float best_ms = 0.0f;
+    const int rec_every = h->rec_every;
+    h->rec_every = 0;   // trials take no probe samples
+    int max_ny = 0;
+    for (int c = 0; c < h->n_cav; ++c) max_ny = std::max(max_ny, h->desc[c].ny);
+    for (int seg : kSegCandidates) {
+        if (rc) break;
+        if (seg > max_ny && seg != kSegCandidates[sizeof(kSegCandidates) / sizeof(kSegCandidates[0]) - 1]) continue;
+        h->opt.segment_rows = seg;
+        rc = rebuild_worklists(h);
+        if (!rc) rc = eager_steps(h, 1);   // warm-up
+        if (!rc && hipEventRecord(e0, h->stream) != hipSuccess) rc = fail(IFDLBM_EDEVICE, "hipEventRecord");
+        if (!rc) rc = eager_steps(h, steps_per_trial);
+        if (!rc && hipEventRecord(e1, h->stream) != hipSuccess) rc = fail(IFDLBM_EDEVICE, "hipEventRecord");
+        if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = fail(IFDLBM_EDEVICE, "hipEventSynchronize");
+        float ms = 0.0f;
+        if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(IFDLBM_EDEVICE, "hipEventElapsedTime");
+        if (!rc && (best == 0 || ms < best_ms)) {
+            best = seg;
+            best_ms = ms;
+        }
+        if (!rc && restore() != hipSuccess) rc = fail(IFDLBM_EDEVICE, "autotune: state restore");
+    }
+    h->rec_every = rec_every;
+    h->opt.segment_rows = rc ? rows0 : best;
+    int rc2 = rebuild_worklists(h);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(h->stream);
+    for (void* p : {bf, bl, br, static_cast<void*>(bs)})
+        if (p) (void)hipFree(p);
+    if (rc) return rc;
+    if (rc2) return rc2;
+    if (segment_rows) *segment_rows = best;
+    if (ms_per_step) *ms_per_step = best_ms / steps_per_trial;
+    return IFDLBM_OK;
+}
+
 int ifdlbm_info(ifdlbm_t* h, ifdlbm_info_t* info)
 {
     if (!h || !info) return fail(IFDLBM_EINVAL, "null argument");
@@ -875,6 +954,101 @@ int ifdlbm_gradient(const ifdlbm_cavity* cav, const ifdlbm_options* opt, int64_t
     if (e != hipSuccess)
         return fail(e == hipErrorOutOfMemory ? IFDLBM_ENOMEM : IFDLBM_EDEVICE, err);
     return IFDLBM_OK;
+}
+
+int ifdlbm_adjoint(const ifdlbm_cavity* cav, const ifdlbm_options* opt, int64_t n_steps, int32_t checkpoint_every,
+                   int32_t objective, double* J, double grad[3])
+{
+    if (!cav || !opt || !J || !grad) return fail(IFDLBM_EINVAL, "null argument");
+    if (objective != IFDLBM_OBJ_KINETIC_ENERGY) return fail(IFDLBM_EINVAL, "unknown objective");
+    if (n_steps < 1) return fail(IFDLBM_EINVAL, "n_steps must be >= 1");
+    if (checkpoint_every < 1) return fail(IFDLBM_EINVAL, "checkpoint_every must be >= 1");
+    if (opt->lambda_mode != IFDLBM_LAMBDA_LAGGED)
+        return fail(IFDLBM_EINVAL, "the adjoint follows the lagged lambda of Step (2)");
+    ifdlbm_options o = *opt;
+    o.graph_steps = 0;                 // one eager call per step: recomputation draws the same random words
+    o.residual_every = 1 << 30;        // no residual work inside the sweeps
+    o.batched = 1;
+    ifdlbm_t* h = nullptr;
+    int rc = ifdlbm_create(cav, 1, &o, &h);
+    if (rc) return rc;
+    const CavityDesc c = h->desc[0];
+    const int prec = h->opt.precision;
+    const size_t nn = (size_t)c.nx * c.ny, sd = 10 * nn;   // doubles per FP64 state
+    const int64_t seg = std::min<int64_t>(checkpoint_every, n_steps);
+    const int64_t n_ck = (n_steps + seg - 1) / seg;
+    const size_t fbytes = h->f_elems * f_elem_size(prec), lbytes = h->l_elems * l_elem_size(prec);
+    char *ck_f = nullptr, *ck_l = nullptr;
+    uint32_t* ck_seed = nullptr;
+    double* traj = nullptr;
+    std::vector<int> ck_cur(n_ck);
+    std::vector<int64_t> ck_count(n_ck);
+    AdjointSweep sweep;
+    hipStream_t s = h->stream;
+    if (!rc) rc = dalloc(&ck_f, fbytes * n_ck);
+    if (!rc) rc = dalloc(&ck_l, lbytes * n_ck);
+    if (!rc) rc = dalloc(&ck_seed, sizeof(uint32_t) * n_ck);
+    if (!rc) rc = dalloc(&traj, sizeof(double) * sd * (seg + 1));
+    if (!rc) {
+        hipError_t e = sweep.init(c, s);
+        if (e != hipSuccess) rc = fail(e == hipErrorOutOfMemory ? IFDLBM_ENOMEM : IFDLBM_EDEVICE,
+                                       std::string("adjoint buffers: ") + hipGetErrorString(e));
+    }
+    auto hip_ok = [&](hipError_t e, const char* what) {
+        if (e == hipSuccess) return true;
+        rc = fail(IFDLBM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+        return false;
+    };
+    auto to_traj = [&](int64_t slot) {
+        return hip_ok(launch_state_out(prec, h->d_f[h->cur], h->d_l[h->cur], c, 0.0, traj + slot * sd,
+                                       traj + slot * sd + 9 * nn, s), "state out");
+    };
+    // forward sweep, keeping the state at every checkpoint
+    for (int64_t q = 0; q < n_ck && !rc; ++q) {
+        ck_cur[q] = h->cur;
+        ck_count[q] = h->step_count;
+        if (!hip_ok(hipMemcpyAsync(ck_f + q * fbytes, h->d_f[h->cur], fbytes, hipMemcpyDeviceToDevice, s), "checkpoint") ||
+            !hip_ok(hipMemcpyAsync(ck_l + q * lbytes, h->d_l[h->cur], lbytes, hipMemcpyDeviceToDevice, s), "checkpoint") ||
+            !hip_ok(hipMemcpyAsync(ck_seed + q, h->d_seed, sizeof(uint32_t), hipMemcpyDeviceToDevice, s), "checkpoint"))
+            break;
+        const int64_t steps = std::min(seg, n_steps - q * seg);
+        for (int64_t t = 0; t < steps && !rc; ++t) rc = eager_steps(h, 1);
+    }
+    // reverse sweep: recompute each segment from its checkpoint, then walk it backwards
+    for (int64_t q = n_ck - 1; q >= 0 && !rc; --q) {
+        h->cur = ck_cur[q];
+        h->step_count = ck_count[q];
+        if (!hip_ok(hipMemcpyAsync(h->d_f[h->cur], ck_f + q * fbytes, fbytes, hipMemcpyDeviceToDevice, s), "restore") ||
+            !hip_ok(hipMemcpyAsync(h->d_l[h->cur], ck_l + q * lbytes, lbytes, hipMemcpyDeviceToDevice, s), "restore") ||
+            !hip_ok(hipMemcpyAsync(h->d_seed, ck_seed + q, sizeof(uint32_t), hipMemcpyDeviceToDevice, s), "restore") ||
+            !to_traj(0))
+            break;
+        const int64_t steps = std::min(seg, n_steps - q * seg);
+        for (int64_t t = 1; t <= steps && !rc; ++t)
+            if (!(rc = eager_steps(h, 1))) to_traj(t);
+        if (rc) break;
+        if (q == n_ck - 1 && !hip_ok(sweep.objective(traj + steps * sd, s), "objective")) break;
+        for (int64_t t = steps - 1; t >= 0 && !rc; --t)
+            hip_ok(sweep.step_back(traj + t * sd, traj + (t + 1) * sd, s), "adjoint step");
+        if (!rc && !hip_ok(hipStreamSynchronize(s), "adjoint segment")) break;
+    }
+    if (!rc) {
+        // derivatives of the parameter rules of ifdlbm_create
+        const ifdlbm_cavity& v = *cav;
+        const double U = std::fabs(v.u_lid), sgn = v.u_lid < 0.0 ? -1.0 : 1.0;
+        const bool contra = o.dt_rule == IFDLBM_DT_CONTRAVARIANT && !((1.0 + c.cot) / c.dxi < 1.0 / c.deta);
+        const double dt_dcot = contra ? -c.dt / (1.0 + c.cot) : 0.0;
+        hipError_t e = sweep.finish(c, dt_dcot, sgn / (v.re * kCs2), -c.K * std::log(U), (2.0 - v.n) * c.K / U * sgn, s,
+                                    J, grad);
+        if (hip_ok(e, "adjoint result") && !(std::isfinite(*J) && std::isfinite(grad[0]) && std::isfinite(grad[1]) &&
+                                             std::isfinite(grad[2])))
+            rc = fail(IFDLBM_EDIVERGED, "the trajectory or its adjoint became non-finite");
+    }
+    (void)hipStreamSynchronize(s);
+    for (void* p : {static_cast<void*>(ck_f), static_cast<void*>(ck_l), static_cast<void*>(ck_seed), static_cast<void*>(traj)})
+        if (p) (void)hipFree(p);
+    ifdlbm_destroy(h);
+    return rc;
 }
 
 int ifdlbm_record(ifdlbm_t* h, int32_t every, int32_t capacity)

@@ -69,7 +69,7 @@ template <int N> __host__ __device__ inline bool operator>=(const Dual<N>& a, co
 template <int N> __host__ __device__ inline bool operator!=(const Dual<N>& a, const Dual<N>& b) { return a.v != b.v; }
 
 // x^y for x > 0: d(x^y) = x^y (y dx / x + ln x dy)
-template <int N> __device__ inline Dual<N> dual_pow(const Dual<N>& x, const Dual<N>& y)
+template <int N> __host__ __device__ inline Dual<N> dual_pow(const Dual<N>& x, const Dual<N>& y)
 {
     const double p = pow(x.v, y.v), lx = log(x.v);
     Dual<N> r(p);

@@ -24,7 +24,7 @@ namespace ifd {
 using D3 = Dual<3>;
 
 template <> __device__ __forceinline__ D3 recip<D3>(D3 x) { return D3(1.0) / x; }
-template <> __device__ __forceinline__ D3 pow_pos<D3>(D3 x, D3 y) { return dual_pow(x, y); }
+template <> __host__ __device__ __forceinline__ D3 pow_pos<D3>(D3 x, D3 y) { return dual_pow(x, y); }
 
 namespace {
 
@@ -54,8 +54,10 @@ __device__ D3 transport_t(const D3* plane, const TParams& c, const D3* geo, int 
 {
     const int cx = cxk(k), cy = cyk(k);
     D3 term(0.0);
+    // the xi term is kept where c_xi is zero: its theta derivative need not be
+    // (the upwind side is then the c >= 0 one, as in the forward step)
     const D3 cxi = geo[j] * (D3((double)cx) - D3((double)cy) * geo[c.ny + i]);
-    if (cxi.v != 0.0) {
+    {
         const D3* row = plane + (int64_t)j * c.nx;
         const bool pos = cxi.v >= 0.0;
         const D3 m2 = (pos && i >= 2) ? row[i - 2] : D3(0.0);

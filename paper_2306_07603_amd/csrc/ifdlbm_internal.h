@@ -106,4 +106,27 @@ hipError_t tangent_kinetic_energy(int nx, int ny, double re, double n, double th
                                   double mix, double gamma_min, int dt_rule, int64_t n_steps, hipStream_t s, double* J,
                                   double* grad, std::string& err);
 
+// Reverse (discrete adjoint) sweep of one cavity's step in FP64.  A state is
+// 9 planes of f-hat deviations then the Lambda plane, [k][j][i] packed, as
+// launch_state_out writes it with rho0 = 0.  Call init once, objective on the
+// final state, step_back(state t, state t + 1) for t = T - 1 down to 0, then
+// finish for J and dJ/d(theta [rad], n, u_lid).
+class AdjointSweep {
+public:
+    AdjointSweep();
+    ~AdjointSweep();
+    AdjointSweep(const AdjointSweep&) = delete;
+    AdjointSweep& operator=(const AdjointSweep&) = delete;
+    hipError_t init(const CavityDesc& c, hipStream_t s);
+    hipError_t objective(const double* state, hipStream_t s);
+    hipError_t step_back(const double* st, const double* st1, hipStream_t s);
+    // dt_dcot, lam0_dU, K_dn, K_dU: derivatives of the handle's parameter rules
+    hipError_t finish(const CavityDesc& c, double dt_dcot, double lam0_dU, double K_dn, double K_dU, hipStream_t s,
+                      double* J, double grad[3]);
+
+private:
+    struct Impl;
+    Impl* d;
+};
+
 }  // namespace ifd

@@ -225,6 +225,7 @@ hipError_t launch_init(int prec, void* f, void* l, const CavityDesc* desc, const
     case P_FP16DEV: hipLaunchKernelGGL(k_init<P_FP16DEV>, dim3(nb), dim3(kNodeBlock), 0, s, f, l, desc, blocks); break;
     case P_FP32X: hipLaunchKernelGGL(k_init<P_FP32X>, dim3(nb), dim3(kNodeBlock), 0, s, f, l, desc, blocks); break;
     case P_FP32SR: hipLaunchKernelGGL(k_init<P_FP32SR>, dim3(nb), dim3(kNodeBlock), 0, s, f, l, desc, blocks); break;
+    case P_FP32SRF: hipLaunchKernelGGL(k_init<P_FP32SRF>, dim3(nb), dim3(kNodeBlock), 0, s, f, l, desc, blocks); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -259,6 +260,7 @@ hipError_t launch_fields(int prec, const void* f, const CavityDesc*, int, const 
     case P_FP16DEV: IFD_FIELDS(P_FP16DEV) break;
     case P_FP32X: IFD_FIELDS(P_FP32X) break;
     case P_FP32SR: IFD_FIELDS(P_FP32SR) break;
+    case P_FP32SRF: IFD_FIELDS(P_FP32SRF) break;
     default: return hipErrorInvalidValue;
     }
 #undef IFD_FIELDS
@@ -275,6 +277,7 @@ hipError_t launch_state_out(int prec, const void* f, const void* l, const Cavity
     case P_FP16DEV: hipLaunchKernelGGL(k_state_out<P_FP16DEV>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
     case P_FP32X: hipLaunchKernelGGL(k_state_out<P_FP32X>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
     case P_FP32SR: hipLaunchKernelGGL(k_state_out<P_FP32SR>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
+    case P_FP32SRF: hipLaunchKernelGGL(k_state_out<P_FP32SRF>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -290,6 +293,7 @@ hipError_t launch_state_in(int prec, void* f, void* l, const CavityDesc& hd, dou
     case P_FP16DEV: hipLaunchKernelGGL(k_state_in<P_FP16DEV>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
     case P_FP32X: hipLaunchKernelGGL(k_state_in<P_FP32X>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
     case P_FP32SR: hipLaunchKernelGGL(k_state_in<P_FP32SR>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
+    case P_FP32SRF: hipLaunchKernelGGL(k_state_in<P_FP32SRF>, g, b, 0, s, f, l, hd, rho0, fhat, lam); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -310,6 +314,7 @@ hipError_t launch_probe(int prec, const void* f, const CavityDesc* desc, int n_c
     case P_FP16DEV: IFD_PROBE(P_FP16DEV) break;
     case P_FP32X: IFD_PROBE(P_FP32X) break;
     case P_FP32SR: IFD_PROBE(P_FP32SR) break;
+    case P_FP32SRF: IFD_PROBE(P_FP32SRF) break;
     default: return hipErrorInvalidValue;
     }
 #undef IFD_PROBE
@@ -326,6 +331,7 @@ hipError_t launch_energy(int prec, const void* f, const CavityDesc*, const doubl
     case P_FP16DEV: hipLaunchKernelGGL(k_energy<P_FP16DEV>, g, b, 0, s, f, hd, partial); break;
     case P_FP32X: hipLaunchKernelGGL(k_energy<P_FP32X>, g, b, 0, s, f, hd, partial); break;
     case P_FP32SR: hipLaunchKernelGGL(k_energy<P_FP32SR>, g, b, 0, s, f, hd, partial); break;
+    case P_FP32SRF: hipLaunchKernelGGL(k_energy<P_FP32SRF>, g, b, 0, s, f, hd, partial); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

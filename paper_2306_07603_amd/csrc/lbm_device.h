@@ -15,7 +15,7 @@
 
 namespace ifd {
 
-enum Precision { P_FP64 = 0, P_FP32 = 1, P_FP16DEV = 2, P_FP32X = 3, P_FP32SR = 4 };
+enum Precision { P_FP64 = 0, P_FP32 = 1, P_FP16DEV = 2, P_FP32X = 3, P_FP32SR = 4, P_FP32SRF = 5 };
 
 // ------------------------------------------------------- random bits
 // Integer mixing function (the "lowbias32" finaliser of C. Wellons's hash
@@ -105,6 +105,7 @@ template <int PREC> struct Storage;
 
 template <> struct Storage<P_FP64> {
     static constexpr bool kStochastic = false;
+    static constexpr bool kExactFinal = false;
     using F = double;
     using L = double;
     using T = double;
@@ -117,6 +118,7 @@ template <> struct Storage<P_FP64> {
 
 template <> struct Storage<P_FP32> {
     static constexpr bool kStochastic = false;
+    static constexpr bool kExactFinal = false;
     using F = float;
     using L = float;
     using T = float;
@@ -130,6 +132,7 @@ template <> struct Storage<P_FP32> {
 // FP32 storage with FP64 arithmetic: only the stored state is rounded to FP32.
 template <> struct Storage<P_FP32X> {
     static constexpr bool kStochastic = false;
+    static constexpr bool kExactFinal = false;
     using F = float;
     using L = float;
     using T = double;
@@ -146,6 +149,7 @@ template <> struct Storage<P_FP32X> {
 // shifts, and can freeze, the fixed point).
 template <> struct Storage<P_FP32SR> {
     static constexpr bool kStochastic = true;
+    static constexpr bool kExactFinal = false;
     using F = float;
     using L = float;
     using T = double;
@@ -157,9 +161,29 @@ template <> struct Storage<P_FP32SR> {
     __device__ static inline void store(F* p, int64_t i, int k, T v) { p[i] = enc(v, k); }
 };
 
+// FP32 storage with stochastic rounding, FP32 arithmetic, except the final
+// update of each stored value: f-hat+ = g + b_hat (e - g) is rebuilt in FP64
+// from the stored (exact) g, the streaming increment of Eq. (3.6), computed in
+// FP32, is added in FP64, and the sum is rounded stochastically.  The rounding
+// errors left in FP32 are those of increments and of the half-step values that
+// only enter difference stencils, not of a stored state.
+template <> struct Storage<P_FP32SRF> {
+    static constexpr bool kStochastic = true;
+    static constexpr bool kExactFinal = true;
+    using F = float;
+    using L = float;
+    using T = float;
+    using V = float;
+    __device__ static inline T cvt(F v, int) { return v; }
+    __device__ static inline F enc(T v, int) { return v; }
+    __device__ static inline F enc_sr(double v, uint32_t r16) { return round_stochastic(v, r16); }
+    __device__ static inline T load(const F* p, int64_t i, int k) { return cvt(p[i], k); }
+    __device__ static inline void store(F* p, int64_t i, int k, T v) { p[i] = enc(v, k); }
+};
+
 // Encoding of a new state population: stochastic rounding where the storage asks for it.
-template <typename S>
-__device__ __forceinline__ typename S::F encode_state(typename S::T v, int k, const NodeWords* nw)
+template <typename S, typename X>
+__device__ __forceinline__ typename S::F encode_state(X v, int k, const NodeWords* nw)
 {
     if constexpr (S::kStochastic)
         return S::enc_sr(v, nw->r16(k));
@@ -171,6 +195,7 @@ __device__ __forceinline__ typename S::F encode_state(typename S::T v, int k, co
 // nine planes on the same O(3 P + 3 c.u) scale, inside FP16's normal range.
 template <> struct Storage<P_FP16DEV> {
     static constexpr bool kStochastic = false;
+    static constexpr bool kExactFinal = false;
     using F = __half;
     using L = float;
     using T = float;
@@ -221,6 +246,17 @@ __device__ __forceinline__ void equilibrium(T P, T ux, T uy, T e[9])
     e[8] = w5 * q(ux - uy);
 }
 
+// Population k of Eq. (2.8) alone (same arithmetic as equilibrium()).
+template <typename T>
+__device__ __forceinline__ T equilibrium_k(T P, T ux, T uy, int k)
+{
+    const T uu = ux * ux + uy * uy;
+    const T base = T(3) * P - T(1.5) * uu;
+    const T w = k < 5 ? T(1) / T(9) : T(1) / T(36);
+    const T cu = T(cxk(k)) * ux + T(cyk(k)) * uy;
+    return k == 0 ? T(-5) / T(3) * P - T(2) / T(3) * uu : w * (base + cu * (T(3) + T(4.5) * cu));
+}
+
 // 1/x for x > 0: v_rcp_f32 (1 ulp) in FP32; v_rcp_f64 refined by two Newton
 // steps r <- r (2 - x r) in FP64 (relative error squares at each step).
 template <typename T> __device__ __forceinline__ T recip(T x);
@@ -233,12 +269,16 @@ template <> __device__ __forceinline__ double recip<double>(double x)
     return r;
 }
 
-template <typename T> __device__ __forceinline__ T pow_pos(T x, T y);
-template <> __device__ __forceinline__ double pow_pos<double>(double x, double y) { return pow(x, y); }
-template <> __device__ __forceinline__ float pow_pos<float>(float x, float y)
+template <typename T> __host__ __device__ __forceinline__ T pow_pos(T x, T y);
+template <> __host__ __device__ __forceinline__ double pow_pos<double>(double x, double y) { return pow(x, y); }
+template <> __host__ __device__ __forceinline__ float pow_pos<float>(float x, float y)
 {
-    // x >= gamma_min^2 > 0 is a normal float: v_log_f32 / v_exp_f32 (base 2)
+    // x >= gamma_min^2 > 0 is a normal float: v_log_f32 / v_exp_f32 (base 2) on the device
+#ifdef __HIP_DEVICE_COMPILE__
     return __builtin_amdgcn_exp2f(y * __builtin_amdgcn_logf(x));
+#else
+    return exp2f(y * log2f(x));
+#endif
 }
 
 // Step (2): lambda from the non-equilibrium second moment, Eqs. (2.12)-(2.14)
@@ -251,7 +291,7 @@ template <typename T>
 struct PowerLaw {
     T K3, expo, g2min, dt, lam_newton;
     bool newtonian, implicit;
-    __device__ __forceinline__ explicit PowerLaw(const CavityDesc& c)
+    __host__ __device__ __forceinline__ explicit PowerLaw(const CavityDesc& c)
         : K3(T(3) * T(c.K)), expo(T(c.expo)), g2min(T(c.g2min)), dt(T(c.dt)), lam_newton(T(c.lam_newton)),
           newtonian(c.newtonian != 0), implicit(c.implicit_lambda != 0)
     {
@@ -265,7 +305,7 @@ struct PowerLaw {
 // Newton steps h' = 1 + 4 expo map / s from the lagged value, replaced by
 // bisection of the bracket whenever a step leaves it or h' <= 0.
 template <typename V>
-__device__ __forceinline__ V implicit_relaxation_time(V Q18, V lam0, const PowerLaw<V>& pl)
+__host__ __device__ __forceinline__ V implicit_relaxation_time(V Q18, V lam0, const PowerLaw<V>& pl)
 {
     auto map = [&](V lam, bool& floored) {
         const V s = V(2) * lam + pl.dt;
@@ -277,10 +317,12 @@ __device__ __forceinline__ V implicit_relaxation_time(V Q18, V lam0, const Power
     bool fl;
     V lo = V(0), hi = pl.expo >= V(0) ? map(V(0), fl) : pl.K3 * pow_pos<V>(pl.g2min, pl.expo);
     V lam = lam0 > lo && lam0 < hi ? lam0 : V(0.5) * (lo + hi);
-    const V tol = sizeof(V) == 8 ? V(4e-16) : V(2e-7);
-    for (int it = 0; it < 60; ++it) {
+    // Newton converges quadratically: a step below tol leaves an error far below it
+    const V tol = sizeof(V) == 8 ? V(1e-13) : V(1e-6);
+    for (int it = 0; it < 40; ++it) {
         const V m = map(lam, fl);
         const V h = lam - m;
+        if (h == V(0)) break;   // exact root
         if (h < V(0))
             lo = lam;
         else
@@ -288,10 +330,10 @@ __device__ __forceinline__ V implicit_relaxation_time(V Q18, V lam0, const Power
         const V s = V(2) * lam + pl.dt;
         const V hp = V(1) + (fl ? V(0) : V(4) * pl.expo * m / s);
         V next = hp > V(0) ? lam - h / hp : V(-1);
-        if (!(next > lo && next < hi)) next = V(0.5) * (lo + hi);
+        if (!(next >= lo && next <= hi)) next = V(0.5) * (lo + hi);
         const V step = next > lam ? next - lam : lam - next;
         lam = next;
-        if (step <= tol * lam || !(hi > lo)) break;
+        if (step <= tol * lam) break;
     }
     return lam;
 }

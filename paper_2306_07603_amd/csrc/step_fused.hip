@@ -362,7 +362,8 @@ struct March {
         moments(g, m[0], m[1], m[2]);
     }
 
-    __device__ __forceinline__ void store_row(int row, const T (&x)[9]) const
+    template <typename X>
+    __device__ __forceinline__ void store_row(int row, const X (&x)[9]) const
     {
         const uint32_t vo = foff(row);
         const NodeWords nw(skey, ckey, (uint32_t)(row * pitch + i));
@@ -436,6 +437,10 @@ struct March {
     template <int R>
     __device__ __forceinline__ void row(int t)
     {
+        const int p = t - 4;
+        const bool do_c = p >= j0 && p < j1 && p >= 1 && p <= ny - 2;
+        F gcr[9];   // exact final update: the stored f-hat of row p, read again before stage B
+
         // ------------------------------------------------------------ A: row t
         if (t <= ny - 1) {
             const int hs = hslot(t);
@@ -444,20 +449,44 @@ struct March {
             for (int k = 0; k < 9; ++k) g[k] = S::cvt(gn_[k], k);
             const V lam_old = V(ln_);
             if (t + 1 <= t_last) fetch(t + 1);   // consumed by the next row
-            moments(g, P, ux, uy);
-            equilibrium(P, ux, uy, e);
+            V l;
+            if constexpr (S::kExactFinal) {
+                // e - g in FP64 from the exact stored g: at low shear the non-equilibrium part is far below
+                // an FP32 ulp of g, and Step (2) raises it to the power (n - 1) / 2
+                double gd[9], dd[9], Pd, uxd, uyd;
 #pragma unroll
-            for (int k = 0; k < 9; ++k) d[k] = e[k] - g[k];
-            const V l = relaxation_time_d<IMPL>(d, lam_old, pl);
+                for (int k = 0; k < 9; ++k) gd[k] = (double)g[k];
+                moments(gd, Pd, uxd, uyd);
+#pragma unroll
+                for (int k = 0; k < 9; ++k) {
+                    dd[k] = equilibrium_k(Pd, uxd, uyd, k) - gd[k];
+                    d[k] = T(dd[k]);
+                }
+                l = relaxation_time_d<IMPL>(dd, lam_old, pl);
+            } else {
+                moments(g, P, ux, uy);
+                equilibrium(P, ux, uy, e);
+#pragma unroll
+                for (int k = 0; k < 9; ++k) d[k] = e[k] - g[k];
+                l = relaxation_time_d<IMPL>(d, lam_old, pl);
+            }
             const Relax<V> rx(l, dtv);
             const T b_hat = T(rx.b_hat), b_bar = T(rx.b_bar);
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
                 gbp[sg(R, 0)][k] = g[k] + b_bar * d[k];
-                sh.hp[hs][k][lane] = g[k] + b_hat * d[k];
+                if constexpr (!S::kExactFinal) sh.hp[hs][k][lane] = g[k] + b_hat * d[k];
             }
             lam[sg(R, 0)] = l;
             if (out_col && t >= j0 && t < j1) Buf<L>::st(L(l), rl_out, loff(t), 0u);
+        }
+
+        if constexpr (S::kExactFinal) {
+            if (do_c) {
+                const uint32_t vo = foff(p);
+#pragma unroll
+                for (int k = 0; k < 9; ++k) gcr[k] = Buf<F>::ld(rf_in, vo, (uint32_t)k * fpb);
+            }
         }
 
         // ------------------------------------------------------------ B: row t - 2
@@ -507,26 +536,54 @@ struct March {
         }
 
         // ------------------------------------------------------------ C: row t - 4
-        const int p = t - 4;
-        if (p >= j0 && p < j1 && p >= 1 && p <= ny - 2) {
+        if (do_c) {
             T hp[9], gn[9];
-            const int hs = hslot(p);
-#pragma unroll
-            for (int k = 0; k < 9; ++k) hp[k] = sh.hp[hs][k][lane];
+            T rem[9];   // exact final update (FP32SRF): value = gn + rem, rem the part below gn's rounding
             eta_ghosts<sf(R, 6), sf(R, 5), sf(R, 4), sf(R, 3), sf(R, 2)>(fh, p == 1, p == ny - 2);
             const MixedWeights<T> mx(eps, sx_c * geo[p]), my(eps, sy_c);
-            transport<sf(R, 6), sf(R, 5), sf(R, 4), sf(R, 3), sf(R, 2)>(fh, hp, mx, my, gn);
+            if constexpr (S::kExactFinal) {
+                // f-hat+ = g + b_hat (e - g) in FP64 from the stored g (Eq. 2.15), plus the FP32 increment
+                double gd[9], P, ux, uy;
+#pragma unroll
+                for (int k = 0; k < 9; ++k) {
+                    gd[k] = (double)S::cvt(gcr[k], k);
+                    hp[k] = T(0);
+                }
+                moments(gd, P, ux, uy);
+                const double bh = (double)Relax<V>(lam[sg(R, 4)], dtv).b_hat;
+                transport<sf(R, 6), sf(R, 5), sf(R, 4), sf(R, 3), sf(R, 2)>(fh, hp, mx, my, gn);
+#pragma unroll
+                for (int k = 0; k < 9; ++k) {
+                    const double gk = (double)S::cvt(gcr[k], k);
+                    const double v = (gk + bh * (equilibrium_k(P, ux, uy, k) - gk)) + (double)gn[k];
+                    gn[k] = T(v);
+                    rem[k] = T(v - (double)gn[k]);
+                }
+            } else {
+                const int hs = hslot(p);
+#pragma unroll
+                for (int k = 0; k < 9; ++k) hp[k] = sh.hp[hs][k][lane];
+                transport<sf(R, 6), sf(R, 5), sf(R, 4), sf(R, 3), sf(R, 2)>(fh, hp, mx, my, gn);
+            }
+            const bool wall_lane = i == 0 || i == nx - 1;
             if (walls_c) {
                 publish(sh.wc, i, nx, gn);
                 wave_sync();
-                if (i == 0 || i == nx - 1) {
+                if (wall_lane) {
                     T src[9];
                     wall_source(sh.wc, i, nx, gn, src);
                     extrapolate(src, T(0), gn);
                 }
             }
             if (out_col) {
-                store_row(p, gn);
+                if constexpr (S::kExactFinal) {
+                    double fin[9];
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) fin[k] = wall_lane ? (double)gn[k] : (double)gn[k] + (double)rem[k];
+                    store_row(p, fin);
+                } else {
+                    store_row(p, gn);
+                }
                 if (RES) {
                     T old[3];
                     old_moments(p, old);
@@ -661,6 +718,7 @@ hipError_t fused_prec(int prec, const StepArgs& a, const StripItem* items, int w
     case P_FP16DEV: return fused<P_FP16DEV, IMPL>(a, items, w0, nw, residual, s);
     case P_FP32X: return fused<P_FP32X, IMPL>(a, items, w0, nw, residual, s);
     case P_FP32SR: return fused<P_FP32SR, IMPL>(a, items, w0, nw, residual, s);
+    case P_FP32SRF: return fused<P_FP32SRF, IMPL>(a, items, w0, nw, residual, s);
     }
     return hipErrorInvalidValue;
 }

@@ -78,13 +78,29 @@ __global__ __launch_bounds__(kNodeBlock) void k_stage_a(StepArgs a, const NodeBl
     T g[9], e[9], d[9], P, ux, uy;
 #pragma unroll
     for (int k = 0; k < 9; ++k) g[k] = S::load(f, c.f_off + k * c.plane + r.id, k);
-    moments(g, P, ux, uy);
-    equilibrium(P, ux, uy, e);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) d[k] = e[k] - g[k];
     const PowerLaw<V> pl(c);
-    const V lam = pl.implicit ? relaxation_time_d<true>(d, V(l[c.l_off + r.id]), pl)
-                              : relaxation_time_d<false>(d, V(l[c.l_off + r.id]), pl);
+    V lam;
+    if constexpr (S::kExactFinal) {
+        // e - g in FP64 from the exact stored g (the non-equilibrium part at low shear is below an FP32 ulp)
+        double gd[9], dd[9], Pd, uxd, uyd;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) gd[k] = (double)g[k];
+        moments(gd, Pd, uxd, uyd);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            dd[k] = equilibrium_k(Pd, uxd, uyd, k) - gd[k];
+            d[k] = T(dd[k]);
+        }
+        lam = pl.implicit ? relaxation_time_d<true>(dd, V(l[c.l_off + r.id]), pl)
+                          : relaxation_time_d<false>(dd, V(l[c.l_off + r.id]), pl);
+    } else {
+        moments(g, P, ux, uy);
+        equilibrium(P, ux, uy, e);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) d[k] = e[k] - g[k];
+        lam = pl.implicit ? relaxation_time_d<true>(d, V(l[c.l_off + r.id]), pl)
+                          : relaxation_time_d<false>(d, V(l[c.l_off + r.id]), pl);
+    }
     const Relax<V> rx(lam, V(c.dt));
     const T b_hat = T(rx.b_hat), b_bar = T(rx.b_bar);
     T* hp = static_cast<T*>(a.hat_plus);
@@ -166,6 +182,26 @@ __global__ __launch_bounds__(kNodeBlock) void k_stage_c(StepArgs a, const NodeBl
     const T* geo = geo_table<T>(a);
     const T dt = T(c.dt);
     const NodeWords nw(step_key(a.seed_ctr[0], a.step), cavity_key(c.index), (uint32_t)r.id);
+    if constexpr (S::kExactFinal) {
+        // f-hat+ rebuilt in FP64 from the stored f-hat (Eq. 2.15), the FP32 increment added in FP64
+        using V = typename S::V;
+        const auto* fin = static_cast<const typename S::F*>(a.f_in);
+        double gd[9], e[9], P, ux, uy;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) gd[k] = (double)S::load(fin, c.f_off + k * c.plane + r.id, k);
+        moments(gd, P, ux, uy);
+        equilibrium(P, ux, uy, e);
+        const double bh = (double)Relax<V>(V(static_cast<const T*>(a.lam_new)[c.l_off + r.id]), V(c.dt)).b_hat;
+#pragma unroll 1
+        for (int k = 0; k < 9; ++k) {
+            const int64_t o = c.f_off + k * c.plane;
+            const T inc = k == 0 ? T(0) : -(dt * transport(fh + o, c, geo, r.i, r.j, k));
+            const double v = (gd[k] + bh * (e[k] - gd[k])) + (double)inc;
+            hp[o + r.id] = T(v);
+            out[o + r.id] = encode_state<S>(v, k, &nw);
+        }
+        return;
+    }
     out[c.f_off + r.id] = encode_state<S>(hp[c.f_off + r.id], 0, &nw);
 #pragma unroll 1
     for (int k = 1; k < 9; ++k) {
@@ -267,6 +303,7 @@ hipError_t launch_staged_step(int prec, const StepArgs& a, const NodeBlock* bloc
     case P_FP16DEV: return staged<P_FP16DEV>(a, blocks, b0, nb, residual, s);
     case P_FP32X: return staged<P_FP32X>(a, blocks, b0, nb, residual, s);
     case P_FP32SR: return staged<P_FP32SR>(a, blocks, b0, nb, residual, s);
+    case P_FP32SRF: return staged<P_FP32SRF>(a, blocks, b0, nb, residual, s);
     }
     return hipErrorInvalidValue;
 }

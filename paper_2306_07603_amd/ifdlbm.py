@@ -30,12 +30,13 @@ IFDLBM_EDEVICE = -3
 IFDLBM_EDIVERGED = -4
 IFDLBM_ENOTCONVERGED = -5
 
-IFDLBM_FP64, IFDLBM_FP32, IFDLBM_FP16DEV, IFDLBM_FP32X, IFDLBM_FP32SR = 0, 1, 2, 3, 4
+IFDLBM_FP64, IFDLBM_FP32, IFDLBM_FP16DEV, IFDLBM_FP32X, IFDLBM_FP32SR, IFDLBM_FP32SRF = 0, 1, 2, 3, 4, 5
 IFDLBM_KERNEL_FUSED, IFDLBM_KERNEL_STAGED = 0, 1
 IFDLBM_DT_CONTRAVARIANT, IFDLBM_DT_CARTESIAN = 0, 1
 IFDLBM_STATUS_RUNNING, IFDLBM_STATUS_CONVERGED, IFDLBM_STATUS_DIVERGED, IFDLBM_STATUS_NOT_CONVERGED = 0, 1, 2, 3
 
-PRECISIONS = {"fp64": IFDLBM_FP64, "fp32": IFDLBM_FP32, "fp16dev": IFDLBM_FP16DEV, "fp32x": IFDLBM_FP32X, "fp32sr": IFDLBM_FP32SR}
+PRECISIONS = {"fp64": IFDLBM_FP64, "fp32": IFDLBM_FP32, "fp16dev": IFDLBM_FP16DEV, "fp32x": IFDLBM_FP32X, "fp32sr": IFDLBM_FP32SR,
+              "fp32srf": IFDLBM_FP32SRF}
 KERNELS = {"fused": IFDLBM_KERNEL_FUSED, "staged": IFDLBM_KERNEL_STAGED}
 
 
@@ -108,6 +109,9 @@ def lib():
         L.ifdlbm_info.argtypes = [_H, ctypes.POINTER(ifdlbm_info_t)]
         L.ifdlbm_gradient.argtypes = [ctypes.POINTER(ifdlbm_cavity), ctypes.POINTER(ifdlbm_options), ctypes.c_int64,
                                       ctypes.c_int32, _D, _D]
+        L.ifdlbm_adjoint.argtypes = [ctypes.POINTER(ifdlbm_cavity), ctypes.POINTER(ifdlbm_options), ctypes.c_int64,
+                                     ctypes.c_int32, ctypes.c_int32, _D, _D]
+        L.ifdlbm_autotune.argtypes = [_H, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _D]
         L.ifdlbm_record.argtypes = [_H, ctypes.c_int32, ctypes.c_int32]
         L.ifdlbm_get_record.argtypes = [_H, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_int64), _D, _D, _D]
@@ -286,6 +290,24 @@ def ifdlbm_gradient(cavity: Cavity, options: Optional[ifdlbm_options] = None, n_
     _check(lib().ifdlbm_gradient(ctypes.byref(cavity.c()), ctypes.byref(options), int(n_steps), int(objective),
                                  ctypes.byref(J), _dptr(grad)))
     return J.value, grad
+
+
+def ifdlbm_adjoint(cavity: Cavity, options: Optional[ifdlbm_options] = None, n_steps: int = 1,
+                   checkpoint_every: int = 500, objective: int = IFDLBM_OBJ_KINETIC_ENERGY):
+    """(J, [dJ/dtheta_rad, dJ/dn, dJ/du_lid]) by the checkpointed discrete adjoint."""
+    options = options or ifdlbm_default_options()
+    J = ctypes.c_double()
+    grad = np.zeros(3)
+    _check(lib().ifdlbm_adjoint(ctypes.byref(cavity.c()), ctypes.byref(options), int(n_steps), int(checkpoint_every),
+                                int(objective), ctypes.byref(J), _dptr(grad)))
+    return J.value, grad
+
+
+def ifdlbm_autotune(h: Handle, steps_per_trial: int = 20):
+    """(segment rows chosen, ms per step) of the fused kernel's tile-shape autotuner."""
+    rows, ms = ctypes.c_int32(0), ctypes.c_double(0.0)
+    _check(lib().ifdlbm_autotune(h.ptr, steps_per_trial, ctypes.byref(rows), ctypes.byref(ms)))
+    return rows.value, ms.value
 
 
 def ifdlbm_record(h: Handle, every: int, capacity: int = 0) -> None:

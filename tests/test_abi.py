@@ -88,3 +88,27 @@ def test_batch_recipe_is_seeded_and_in_range():
         assert 100.0 <= c.re <= 5000.0 and 0.5 <= c.n <= 1.5 and 40.0 <= c.theta_deg <= 90.0
     # SplitMix64 of the published definition: first output for seed 0
     assert M.workloads.splitmix64(0)[1] == 0xE220A8397B1DCDAF
+
+
+def test_gradient_calls_reject_bad_arguments():
+    cav = M.Cavity(17, 17, 100.0, 0.8, 60.0, 0.1)
+    o = M.ifdlbm_default_options()
+    calls = [
+        lambda: M.ifdlbm_adjoint(cav, o, 0, 10),
+        lambda: M.ifdlbm_adjoint(cav, o, 10, 0),
+        lambda: M.ifdlbm_adjoint(cav, o, 10, 5, objective=3),
+        lambda: M.ifdlbm_adjoint(cav, M.ifdlbm_default_options(lambda_mode=M.IFDLBM_LAMBDA_IMPLICIT), 10, 5),
+        lambda: M.ifdlbm_adjoint(M.Cavity(4, 17, 100.0, 0.8, 60.0), o, 10, 5),
+        lambda: M.ifdlbm_adjoint(cav, M.ifdlbm_default_options(cfl=0.0), 10, 5),
+        lambda: M.ifdlbm_gradient(cav, o, 0),
+        lambda: M.ifdlbm_gradient(cav, M.ifdlbm_default_options(lambda_mode=M.IFDLBM_LAMBDA_IMPLICIT), 10),
+    ]
+    for call in calls:
+        with pytest.raises(M.IfdlbmError) as e:
+            call()
+        assert e.value.code == M.IFDLBM_EINVAL
+
+
+def test_autotune_rejects_bad_arguments():
+    L = M.lib()
+    assert L.ifdlbm_autotune(None, 5, None, None) == M.IFDLBM_EINVAL

@@ -1,7 +1,9 @@
-"""dJ/d(theta, n, U) of the kinetic energy after a fixed number of steps:
-tangent-linear sweep of the library against central differences of the FP64
-forward (h = 1e-4) and against Richardson-extrapolated differences of the
-CPU oracle; and the torch.autograd.Function over it."""
+"""dJ/d(theta, n, U) of the kinetic energy after a fixed number of steps: the
+tangent-linear sweep and the checkpointed discrete adjoint of the library
+against each other (both are the exact derivative of the same discrete map),
+against central differences of the FP64 forward (h = 1e-4) and against
+Richardson-extrapolated differences of the CPU oracle; and the
+torch.autograd.Function over them."""
 import math
 
 import numpy as np
@@ -42,7 +44,8 @@ def test_gradient_against_central_differences():
         assert err <= 1e-4
 
 
-def test_gradient_against_oracle_differences():
+@pytest.mark.parametrize("method", ["tangent", "adjoint"])
+def test_gradient_against_oracle_differences(method):
     """17 x 17, 120 steps: Richardson extrapolation of oracle central
     differences (h and h/2) is accurate to about 1e-9 relative."""
     n_xi = n_eta = 17
@@ -62,20 +65,88 @@ def test_gradient_against_oracle_differences():
     ref = [deriv(lambda d: ke(th + math.degrees(d), n, u), 1e-3),
            deriv(lambda d: ke(th, n + d, u), 1e-3),
            deriv(lambda d: ke(th, n, u + d), 1e-4)]
-    J, g = M.ifdlbm_gradient(M.Cavity(n_xi, n_eta, re, n, th, u), M.ifdlbm_default_options(), steps)
+    cav = M.Cavity(n_xi, n_eta, re, n, th, u)
+    if method == "tangent":
+        J, g = M.ifdlbm_gradient(cav, M.ifdlbm_default_options(), steps)
+    else:
+        J, g = M.ifdlbm_adjoint(cav, M.ifdlbm_default_options(), steps, 50)
     for q in range(3):
         err = abs(g[q] - ref[q]) / abs(ref[q])
-        print("param %d tangent %.12e oracle %.12e rel %.2e" % (q, g[q], ref[q], err), flush=True)
+        print("param %d %s %.12e oracle %.12e rel %.2e" % (q, method, g[q], ref[q], err), flush=True)
         assert err <= 1e-6
 
 
-def test_autograd_function():
+@pytest.mark.parametrize("method", ["tangent", "adjoint"])
+def test_autograd_function(method):
     import torch
     from paper_2306_07603_amd.autograd import cavity_kinetic_energy
     theta = torch.tensor(math.radians(60.0), dtype=torch.float64, requires_grad=True)
     n = torch.tensor(0.7, dtype=torch.float64, requires_grad=True)
     u = torch.tensor(0.1, dtype=torch.float64, requires_grad=True)
-    J = cavity_kinetic_energy(theta, n, u, 25, 25, 200.0, 100)
+    J = cavity_kinetic_energy(theta, n, u, 25, 25, 200.0, 100, None, 30, method)
     (2.0 * J).backward()
     _, g = M.ifdlbm_gradient(M.Cavity(25, 25, 200.0, 0.7, 60.0, 0.1), M.ifdlbm_default_options(), 100)
-    assert np.allclose([theta.grad.item(), n.grad.item(), u.grad.item()], 2.0 * g, rtol=1e-12, atol=0)
+    assert np.allclose([theta.grad.item(), n.grad.item(), u.grad.item()], 2.0 * g, rtol=1e-9, atol=0)
+    with torch.no_grad():
+        J2 = cavity_kinetic_energy(theta, n, u, 25, 25, 200.0, 100)
+    assert abs(J2.item() - J.item()) <= 1e-12 * J.item()
+
+
+ADJ_CASES = [
+    # n_xi, n_eta, Re, n, theta, U, steps, options
+    (33, 33, 150.0, 0.7, 60.0, 0.1, 300, {}),
+    (29, 37, 400.0, 1.3, 45.0, 0.08, 200, {"dt_rule": M.IFDLBM_DT_CARTESIAN, "mix": 0.7}),
+    (25, 25, 100.0, 0.6, 90.0, 0.1, 150, {}),
+    (21, 27, 250.0, 1.0, 70.0, -0.1, 150, {"cfl": 0.3}),
+    (17, 17, 50.0, 0.5, 40.0, 0.1, 400, {"gamma_min": 1e-2}),
+]
+
+
+@pytest.mark.parametrize("kernel", ["staged", "fused"])
+@pytest.mark.parametrize("case", ADJ_CASES, ids=lambda c: "%dx%d_n%g_th%g" % (c[0], c[1], c[3], c[4]))
+def test_adjoint_equals_tangent(kernel, case):
+    """Reverse and forward differentiation of one discrete map: equal up to
+    FP64 rounding (1e-9 relative per component)."""
+    nx, ny, re, n, th, u, steps, opt = case
+    cav = M.Cavity(nx, ny, re, n, th, u)
+    o = M.ifdlbm_default_options(kernel=kernel, **opt)
+    Jt, gt = M.ifdlbm_gradient(cav, o, steps)
+    Ja, ga = M.ifdlbm_adjoint(cav, o, steps, 64)
+    print(case, kernel, "tangent", gt, "adjoint", ga, flush=True)
+    assert abs(Ja - Jt) <= 1e-11 * abs(Jt)
+    for q in range(3):
+        assert abs(ga[q] - gt[q]) <= 1e-9 * abs(gt[q]) + 1e-13 * np.abs(gt).max(), q
+
+
+def test_adjoint_does_not_depend_on_checkpoint_spacing():
+    cav = M.Cavity(33, 29, 300.0, 0.8, 55.0, 0.1)
+    o = M.ifdlbm_default_options(kernel="fused")
+    res = [M.ifdlbm_adjoint(cav, o, 150, c) for c in (1, 7, 64, 150, 1000)]
+    for J, g in res[1:]:
+        assert J == res[0][0] and np.array_equal(g, res[0][1])
+
+
+@pytest.mark.parametrize("precision", ["fp32sr", "fp64"])
+def test_adjoint_129_20k_steps(precision):
+    """129 x 129, Re 400, n 0.7, theta 60, 20k steps (FP32 storage with
+    stochastic rounding, and FP64), checkpoints every 500 steps: within 1e-4 of central differences
+    (h = 1e-4) of the FP64 forward."""
+    nx = ny = 129
+    re, n, th, u, steps = 400.0, 0.7, 60.0, 0.1, 20000
+
+    def ke(theta_deg, nn, uu):
+        return ke_forward(nx, ny, re, nn, theta_deg, uu, steps)
+
+    h = 1e-4
+    fd = [(ke(th + math.degrees(h), n, u) - ke(th - math.degrees(h), n, u)) / (2 * h),
+          (ke(th, n + h, u) - ke(th, n - h, u)) / (2 * h),
+          (ke(th, n, u + h * u) - ke(th, n, u - h * u)) / (2 * h * u)]
+    J, g = M.ifdlbm_adjoint(M.Cavity(nx, ny, re, n, th, u),
+                            M.ifdlbm_default_options(precision=precision, kernel="fused"), steps, 500)
+    J64 = ke(th, n, u)
+    print(precision, "J", J, J64, "adjoint", g, "central", fd, flush=True)
+    assert abs(J - J64) <= 1e-4 * J64
+    for q in range(3):
+        err = abs(g[q] - fd[q]) / abs(fd[q])
+        print("param %d rel %.2e" % (q, err), flush=True)
+        assert err <= 1e-4

@@ -156,7 +156,7 @@ def test_graph_equals_eager_bitwise(kernel, precision):
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
-@pytest.mark.parametrize("precision", ["fp32", "fp32sr"])
+@pytest.mark.parametrize("precision", ["fp32", "fp32sr", "fp32srf"])
 def test_rerun_bitwise(kernel, precision):
     specs = [W.CavitySpec(65, 65, 800.0, 0.6, 50.0)]
     a = M.ifdlbm_get_state(gpu(specs, 50, precision, kernel), 0)
@@ -165,13 +165,14 @@ def test_rerun_bitwise(kernel, precision):
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
-def test_fp32sr_graph_replay_equals_eager_calls_bitwise(kernel):
+@pytest.mark.parametrize("precision", ["fp32sr", "fp32srf"])
+def test_fp32sr_graph_replay_equals_eager_calls_bitwise(kernel, precision):
     """Stochastic rounding draws its random words from a counter bumped once
     per call (eager) or per replay (graph) and the step index within it: a
     replay of G steps and an eager call of G steps store the same values."""
     specs = [W.CavitySpec(33, 33, 100.0, 0.8, 60.0), W.CavitySpec(65, 65, 500.0, 1.3, 50.0)]
-    he = gpu(specs, 0, "fp32sr", kernel, residual_every=5)
-    hg = gpu(specs, 0, "fp32sr", kernel, residual_every=5, graph_steps=10)
+    he = gpu(specs, 0, precision, kernel, residual_every=5)
+    hg = gpu(specs, 0, precision, kernel, residual_every=5, graph_steps=10)
     for _ in range(3):
         M.ifdlbm_step(he, 10)
         M.ifdlbm_step(hg, 10)
@@ -236,7 +237,7 @@ def test_fp32sr_rounding_is_unbiased(kernel):
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
-@pytest.mark.parametrize("precision", ["fp32", "fp32x", "fp32sr"])
+@pytest.mark.parametrize("precision", ["fp32", "fp32x", "fp32sr", "fp32srf"])
 def test_fp32_against_oracle(kernel, precision):
     spec = W.single_small()
     h = gpu([spec], 2000, precision, kernel)
@@ -297,7 +298,8 @@ def test_run_to_steady_and_fp32_steady_error(kernel):
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
-def test_fp32sr_steady_velocity(kernel):
+@pytest.mark.parametrize("precision", ["fp32sr", "fp32srf"])
+def test_fp32sr_steady_velocity(kernel, precision):
     """Converge FP64 to E <= 1e-10, run FP32 storage with stochastic rounding as
     many steps: the steady velocity stays within 1e-5 of the FP64 one."""
     spec = W.CavitySpec(65, 65, 100.0, 0.8, 60.0)
@@ -305,24 +307,25 @@ def test_fp32sr_steady_velocity(kernel):
     rc, steps, ru, rp = M.ifdlbm_run_to_steady(h64, 1e-10, 400000)
     print("fp64 steady after", steps, ru, rp, flush=True)
     assert rc == M.IFDLBM_OK and M.ifdlbm_status(h64, 0) == M.IFDLBM_STATUS_CONVERGED
-    hsr = gpu([spec], 0, "fp32sr", kernel, residual_every=500, graph_steps=1000)
+    hsr = gpu([spec], 0, precision, kernel, residual_every=500, graph_steps=1000)
     M.ifdlbm_step(hsr, int(steps[0]))
     u64, v64, _ = M.ifdlbm_get_fields(h64, 0)
     u32, v32, _ = M.ifdlbm_get_fields(hsr, 0)
     err = max(rel(u32, u64), rel(v32, v64))
-    print("fp32sr steady velocity error", err, flush=True)
+    print(precision, "steady velocity error", err, flush=True)
     assert err <= FP32_TOL
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
-def test_batch_fp32sr_bench_configuration_against_oracle(kernel):
+@pytest.mark.parametrize("precision", ["fp32sr", "fp32srf"])
+def test_batch_fp32sr_bench_configuration_against_oracle(kernel, precision):
     """The 256-cavity batch exactly as the benchmark times it (FP32 storage with
     stochastic rounding, one launch per step, 100-step graph replays, residual
     sums every 100 steps): after 200 steps, one sampled cavity of every side
     against the FP64 oracle."""
     specs = W.batch_sweep()
     steps = 200
-    h = gpu(specs, steps, "fp32sr", kernel, residual_every=100, graph_steps=100, batched=1)
+    h = gpu(specs, steps, precision, kernel, residual_every=100, graph_steps=100, batched=1)
     picks = []
     for side in (65, 129, 257, 513):
         picks += [i for i, s in enumerate(specs) if s.n_xi == side][:1]
@@ -330,7 +333,7 @@ def test_batch_fp32sr_bench_configuration_against_oracle(kernel):
         u, v, p = M.ifdlbm_get_fields(h, c)
         uo, vo, po, _, _ = O.simulate(oparams(specs[c]), steps)
         errs = (rel(u, uo), rel(v, vo), rel(p, po))
-        print(c, specs[c], "fp32sr errors u v P", errs, flush=True)
+        print(c, specs[c], precision, "errors u v P", errs, flush=True)
         assert errs[0] <= FP32_TOL and errs[1] <= FP32_TOL, c
 
 
@@ -374,3 +377,25 @@ def test_fused_segmentation_does_not_change_results(rows):
     for c in range(2):
         a, b = M.ifdlbm_get_state(ref, c), M.ifdlbm_get_state(h, c)
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), c
+
+
+@pytest.mark.parametrize("precision", ["fp32sr", "fp64"])
+def test_autotune_keeps_state_and_results(precision):
+    """The tile-shape autotuner restores the state, step count and random-word
+    counter: stepping after it is bitwise equal to stepping without it."""
+    specs = [W.CavitySpec(129, 129, 400.0, 0.8, 60.0), W.CavitySpec(65, 97, 1000.0, 1.3, 45.0)]
+    ref = gpu(specs, 20, precision, "fused")
+    M.ifdlbm_step(ref, 15)
+    h = gpu(specs, 20, precision, "fused")
+    rows, ms = M.ifdlbm_autotune(h, 5)
+    print(precision, rows, ms, flush=True)
+    assert rows in (16, 24, 32, 48, 64, 96, 128) and ms > 0.0
+    M.ifdlbm_step(h, 15)
+    for c in range(2):
+        a, b = M.ifdlbm_get_state(ref, c), M.ifdlbm_get_state(h, c)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), c
+
+
+def test_autotune_staged_is_a_no_op():
+    h = gpu([W.CavitySpec(33, 33, 100.0, 0.8, 60.0)], 3, "fp64", "staged")
+    assert M.ifdlbm_autotune(h, 2) == (0, 0.0)
