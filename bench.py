@@ -32,7 +32,7 @@ WORKLOAD = ("256-cavity uneven batch: sides {65,129,257,513}, Re log-uniform [10
             "one launch per step, HIP-graph replay")
 # storage of the distributions and arithmetic type of each precision mode
 PRECISION = {
-    "fp32srf": ("FP32, stochastic rounding of an FP64 final update", "f32"),
+    "fp32srf": ("FP32, stochastic rounding; FP32 arithmetic, the final update of f-hat summed in FP64", "f32"),
     "fp32sr": ("FP32, stochastic rounding", "f64"),
     "fp32": ("FP32, round to nearest", "f32"),
     "fp32x": ("FP32, round to nearest", "f64"),
@@ -137,7 +137,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--kernel", default="fused", choices=["fused", "staged"])
-    ap.add_argument("--precision", default="fp32sr", choices=["fp32srf", "fp32sr", "fp32", "fp32x", "fp16dev", "fp64"])
+    ap.add_argument("--precision", default="fp32srf", choices=["fp32srf", "fp32sr", "fp32", "fp32x", "fp16dev", "fp64"])
     ap.add_argument("--residual-every", type=int, default=100)
     ap.add_argument("--graph-steps", type=int, default=100)
     ap.add_argument("--plain-steps", type=int, default=100, help="steps of the plain FP64 comparison run (0: skip)")

@@ -127,7 +127,16 @@ struct MixedWeights {
     {
     }
     __device__ __forceinline__ T apply(T a2, T a1, T c0, T f1) const { return ((wc * c0 + wa1 * a1) + wa2 * a2) + wf * f1; }
+    // The same from the differences d1 = c0 - a1, d2 = a1 - a2, df = f1 - a1:
+    // eps df + (1 - eps) (3 d1 - d2).  Neighbouring values agree to many
+    // digits, so in FP32 the weighted sum of the values above loses to
+    // cancellation what the differences keep (an error of order one ulp of f
+    // per step that does not average out over a steady run).
+    __device__ __forceinline__ T apply_diff(T df, T d1, T d2) const { return (wc * d1 - wa2 * d2) + wf * df; }
 };
+
+// Mixed differences from differences first where the distributions are FP32.
+template <typename T> constexpr bool kDiffForm = sizeof(T) == 4;
 
 // Population k of the eta direction moves up (c_ky > 0: 2, 5, 6), down
 // (c_ky < 0: 4, 7, 8) or not at all (0, 1, 3).
@@ -375,9 +384,11 @@ struct March {
     // populations of one row, where D are the signed mixed differences: xi
     // neighbours from the LDS row, eta neighbours from ring slots s[0..4]
     // (rows r-2 .. r+2).  mx carries sx * a_j, my carries sy.
+    // elo / ehi: the row is 1 / ny - 2, where the eta difference of the
+    // populations moving up / down falls back to first order.
     template <int S0, int S1, int S2, int S3, int S4>
     __device__ __forceinline__ void transport(const T (&ring)[kRing][9], const T (&base)[9], const MixedWeights<T>& mx,
-                                              const MixedWeights<T>& my, T (&out)[9])
+                                              const MixedWeights<T>& my, bool elo, bool ehi, T (&out)[9])
     {
         auto& xs = sh.xs;
 #pragma unroll
@@ -407,10 +418,24 @@ struct March {
                 w = xl.ad[pr];
                 if (EDGE) edge = first ? xl.edge_p[pr] : xl.edge_m[pr];
             }
-            if (EDGE) a2 = edge ? T(2) * a1 - c0 : a2;
-            T o = base[k] - w * mx.apply(a2, a1, c0, f1);
-            if (moves_up(k)) o = o - my.apply(ring[S0][k], ring[S1][k], c0, ring[S3][k]);
-            if (moves_down(k)) o = o - my.apply(ring[S4][k], ring[S3][k], c0, ring[S1][k]);
+            T o;
+            if constexpr (kDiffForm<T>) {
+                const T d1 = c0 - a1, d2 = (EDGE && edge) ? d1 : a1 - a2;
+                o = base[k] - w * mx.apply_diff(f1 - a1, d1, d2);
+                if (moves_up(k)) {
+                    const T b1 = c0 - ring[S1][k], b2 = elo ? b1 : ring[S1][k] - ring[S0][k];
+                    o = o - my.apply_diff(ring[S3][k] - ring[S1][k], b1, b2);
+                }
+                if (moves_down(k)) {
+                    const T b1 = c0 - ring[S3][k], b2 = ehi ? b1 : ring[S3][k] - ring[S4][k];
+                    o = o - my.apply_diff(ring[S1][k] - ring[S3][k], b1, b2);
+                }
+            } else {
+                if (EDGE) a2 = edge ? T(2) * a1 - c0 : a2;
+                o = base[k] - w * mx.apply(a2, a1, c0, f1);
+                if (moves_up(k)) o = o - my.apply(ring[S0][k], ring[S1][k], c0, ring[S3][k]);
+                if (moves_down(k)) o = o - my.apply(ring[S4][k], ring[S3][k], c0, ring[S1][k]);
+            }
             out[k] = o;
         }
         wave_sync();
@@ -475,7 +500,9 @@ struct March {
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
                 gbp[sg(R, 0)][k] = g[k] + b_bar * d[k];
-                if constexpr (!S::kExactFinal) sh.hp[hs][k][lane] = g[k] + b_hat * d[k];
+                // exact final update: only the collision increment of f-hat+ (Eq. 2.15); the stored g is added
+                // in FP64 at stage C
+                sh.hp[hs][k][lane] = S::kExactFinal ? b_hat * d[k] : g[k] + b_hat * d[k];
             }
             lam[sg(R, 0)] = l;
             if (out_col && t >= j0 && t < j1) Buf<L>::st(L(l), rl_out, loff(t), 0u);
@@ -496,7 +523,7 @@ struct March {
             if (q >= 1 && q <= ny - 2) {
                 eta_ghosts<sg(R, 4), sg(R, 3), sg(R, 2), sg(R, 1), sg(R, 0)>(gbp, q == 1, q == ny - 2);
                 const MixedWeights<T> mx(eps, sx_b * geo[q]), my(eps, sy_b);
-                transport<sg(R, 4), sg(R, 3), sg(R, 2), sg(R, 1), sg(R, 0)>(gbp, gbp[sg(R, 2)], mx, my, fb);
+                transport<sg(R, 4), sg(R, 3), sg(R, 2), sg(R, 1), sg(R, 0)>(gbp, gbp[sg(R, 2)], mx, my, q == 1, q == ny - 2, fb);
                 if (walls_b) {
                     publish(sh.wb, i, nx, fb);
                     wave_sync();
@@ -542,20 +569,15 @@ struct March {
             eta_ghosts<sf(R, 6), sf(R, 5), sf(R, 4), sf(R, 3), sf(R, 2)>(fh, p == 1, p == ny - 2);
             const MixedWeights<T> mx(eps, sx_c * geo[p]), my(eps, sy_c);
             if constexpr (S::kExactFinal) {
-                // f-hat+ = g + b_hat (e - g) in FP64 from the stored g (Eq. 2.15), plus the FP32 increment
-                double gd[9], P, ux, uy;
+                // f-hat(t + dt) = g + (collision increment + streaming increment): the two increments in FP32
+                // (each accurate relative to itself), their sum added to the stored g in FP64
+                const int hs = hslot(p);
+#pragma unroll
+                for (int k = 0; k < 9; ++k) hp[k] = sh.hp[hs][k][lane];
+                transport<sf(R, 6), sf(R, 5), sf(R, 4), sf(R, 3), sf(R, 2)>(fh, hp, mx, my, p == 1, p == ny - 2, gn);
 #pragma unroll
                 for (int k = 0; k < 9; ++k) {
-                    gd[k] = (double)S::cvt(gcr[k], k);
-                    hp[k] = T(0);
-                }
-                moments(gd, P, ux, uy);
-                const double bh = (double)Relax<V>(lam[sg(R, 4)], dtv).b_hat;
-                transport<sf(R, 6), sf(R, 5), sf(R, 4), sf(R, 3), sf(R, 2)>(fh, hp, mx, my, gn);
-#pragma unroll
-                for (int k = 0; k < 9; ++k) {
-                    const double gk = (double)S::cvt(gcr[k], k);
-                    const double v = (gk + bh * (equilibrium_k(P, ux, uy, k) - gk)) + (double)gn[k];
+                    const double v = (double)S::cvt(gcr[k], k) + (double)gn[k];
                     gn[k] = T(v);
                     rem[k] = T(v - (double)gn[k]);
                 }
@@ -563,7 +585,7 @@ struct March {
                 const int hs = hslot(p);
 #pragma unroll
                 for (int k = 0; k < 9; ++k) hp[k] = sh.hp[hs][k][lane];
-                transport<sf(R, 6), sf(R, 5), sf(R, 4), sf(R, 3), sf(R, 2)>(fh, hp, mx, my, gn);
+                transport<sf(R, 6), sf(R, 5), sf(R, 4), sf(R, 3), sf(R, 2)>(fh, hp, mx, my, p == 1, p == ny - 2, gn);
             }
             const bool wall_lane = i == 0 || i == nx - 1;
             if (walls_c) {

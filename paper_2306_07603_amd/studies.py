@@ -96,7 +96,8 @@ def regime(n_side: int = 257, time_units: float = 3000.0, every: int = 50, preci
             "steady_tol": steady_tol, "steps": steps, "seconds": time.time() - t0, "cases": out}
 
 
-def precision(n_side: int = 257, tol: float = 1e-8, max_steps: int = 2000000) -> dict:
+def precision(n_side: int = 257, tol: float = 1e-8, max_steps: int = 2000000,
+              modes=("fp32srf", "fp32sr", "fp32", "fp32x", "fp16dev")) -> dict:
     """Steady states of Re = 1000, n in {0.5, 1, 1.5} x theta in {45, 60, 90}
     in FP64 to E(u), E(P) <= tol, then the FP32 storage modes for as many steps."""
     specs = [(th, n) for n in (0.5, 1.0, 1.5) for th in (45.0, 60.0, 90.0)]
@@ -109,7 +110,7 @@ def precision(n_side: int = 257, tol: float = 1e-8, max_steps: int = 2000000) ->
     stat = [M.ifdlbm_status(h64, c) for c in range(len(cav))]
     res = {"study": "precision", "n_side": n_side, "tol": tol, "cases": []}
     errs = {}
-    for prec in ("fp32srf", "fp32sr", "fp32", "fp32x", "fp16dev"):
+    for prec in modes:
         h = M.ifdlbm_create(cav, M.ifdlbm_default_options(precision=prec, residual_every=1000, graph_steps=1000))
         e = []
         # every cavity runs as many steps as its FP64 run took: step the batch to the largest count and read
@@ -236,10 +237,17 @@ def main(argv=None) -> int:
     ap.add_argument("name", choices=sorted(STUDIES))
     ap.add_argument("--out", default="")
     ap.add_argument("--time-units", type=float, default=None, help="regime / stress: simulated time")
+    ap.add_argument("--modes", default="", help="precision: comma-separated FP32 storage modes to compare")
+    ap.add_argument("--max-steps", type=int, default=None, help="precision: step limit of the FP64 runs")
     args = ap.parse_args(argv)
     kw = {}
     if args.time_units is not None and args.name in ("regime", "stress"):
         kw["time_units"] = args.time_units
+    if args.name == "precision":
+        if args.modes:
+            kw["modes"] = tuple(args.modes.split(","))
+        if args.max_steps:
+            kw["max_steps"] = args.max_steps
     res = STUDIES[args.name](**kw)
     text = json.dumps(res, indent=1, default=float)
     if args.out:
