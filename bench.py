@@ -27,6 +27,7 @@ if ROOT not in sys.path:
 
 METRIC = "MLUPS & % HBM roofline, FP32-batched vs plain FP64 on GPU at ≤1e-5 vs oracle"
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, published
+VALU_PEAK_GINST = 256 * 4 * 2.4 / 4   # wave64 VALU instructions per ns: 256 CUs, 4 SIMD16 each, 2.4 GHz
 WORKLOAD = ("256-cavity uneven batch: sides {65,129,257,513}, Re log-uniform [100,5000], n uniform [0.5,1.5], "
             "theta uniform [40,90] deg, lid 0.1, CFL 0.5; FP64 residual sums every 100 steps, "
             "one launch per step, HIP-graph replay")
@@ -61,11 +62,12 @@ def kernel_source_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(precision: str):
-    """HBM bytes per launch of the step kernel from the rocprofv3 FETCH_SIZE and
-    WRITE_SIZE passes recorded in profiles/ (each scaled by the same counter's
-    reading for a plain copy of known size), or None when the record is absent
-    or was taken on other kernel sources."""
+def measured_record(precision: str, what: str):
+    """A per-launch figure of the step kernel recorded in profiles/ from rocprofv3
+    counter passes: what = "bytes" (FETCH_SIZE and WRITE_SIZE, each scaled by the
+    same counter's reading for a plain copy of known size) or "valu_insts"
+    (SQ_INSTS_VALU, wavefront instructions).  None when the record is absent or
+    was taken on other kernel sources."""
     if not os.path.exists(TRAFFIC_RECORD):
         return None
     rec = {}
@@ -76,7 +78,7 @@ def measured_traffic(precision: str):
                 rec[k.strip()] = v.strip()
     if rec.get("kernel_sources_sha256") != kernel_source_digest():
         return None
-    key = "bytes_per_launch_" + precision
+    key = "%s_per_launch_%s" % (what, precision)
     return float(rec[key]) if key in rec else None
 
 
@@ -140,6 +142,8 @@ def main() -> int:
     ap.add_argument("--precision", default="fp32srf", choices=["fp32srf", "fp32sr", "fp32", "fp32x", "fp16dev", "fp64"])
     ap.add_argument("--residual-every", type=int, default=100)
     ap.add_argument("--graph-steps", type=int, default=100)
+    ap.add_argument("--autotune-steps", type=int, default=10,
+                    help="steps per trial of the segment-length autotuner before timing (0: automatic choice)")
     ap.add_argument("--plain-steps", type=int, default=100, help="steps of the plain FP64 comparison run (0: skip)")
     ap.add_argument("--other-steps", type=int, default=300,
                     help="steps of each other FP32-storage mode, reported beside the headline (0: skip)")
@@ -170,6 +174,10 @@ def main() -> int:
     opt = M.ifdlbm_default_options(precision=args.precision, kernel=args.kernel, residual_every=args.residual_every,
                                    graph_steps=args.graph_steps, batched=1, hip_stream=stream.cuda_stream)
     h = M.ifdlbm_create(cav, opt)
+    seg_rows = None
+    if args.autotune_steps > 0:
+        seg_rows, tuned_ms = M.ifdlbm_autotune(h, args.autotune_steps)
+        log("autotune: %d-row segments, %.3f ms/step in its trials" % (seg_rows, tuned_ms))
     info = M.ifdlbm_info(h)
     log("created %d cavities, %d nodes per step, %d work items" % (info["n_cavities"], info["nodes"], info["work_items"]))
     wall, ev_ms = time_steps(M, h, stream, args.steps, args.warmup)
@@ -185,6 +193,14 @@ def main() -> int:
     alg_bytes = nodes * info["alg_bytes_per_node"]
     achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
     log(args.precision + " batched: %.1f MLUPS, %.3f ms/step, kernel %.3f ms, %.0f GB/s" % (mlups, wall * 1e3 / args.steps, kernel_ms, achieved))
+    # the vector-ALU issue rate of the same launches: SQ_INSTS_VALU per launch (counter record) over the
+    # measured launch time, against 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per wave64 instruction
+    insts = measured_record(args.precision, "valu_insts")
+    valu = None
+    if insts:
+        rate = insts / (kernel_ms * 1e-3) / 1e9
+        valu = {"achieved": rate, "peak": VALU_PEAK_GINST, "unit": "G wave64 VALU instructions/s",
+                "frac": rate / VALU_PEAK_GINST, "insts_per_launch": insts}
     h.close()
 
     plain = None
@@ -224,11 +240,12 @@ def main() -> int:
         "config": {"workload": WORKLOAD, "cavities": len(specs), "nodes_per_step": nodes, "kernel": args.kernel,
                    "precision": args.precision, "storage": PRECISION[args.precision][0],
                    "diverged_cavities": diverged,
-                   "residual_every": args.residual_every, "graph_steps": args.graph_steps},
+                   "residual_every": args.residual_every, "graph_steps": args.graph_steps,
+                   "segment_rows": seg_rows, "autotune_steps": args.autotune_steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.precision),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_record(args.precision, "bytes"),
                      "kernel_ms": kernel_ms, "alg_bytes_per_launch": alg_bytes,
-                     "alg_bytes_per_node": info["alg_bytes_per_node"]},
+                     "alg_bytes_per_node": info["alg_bytes_per_node"], "valu": valu},
         "fp64_plain": plain,
         "other_fp32_storage_modes": other or None,
         "speedup_vs_fp64_plain": (mlups / plain["value"]) if plain else None,
