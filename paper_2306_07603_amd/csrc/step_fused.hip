@@ -52,6 +52,9 @@ constexpr int kRing = 5;                         // ring slots: rows t - 4 .. t
 #ifndef IFD_FUSED_ONE_PATH
 #define IFD_FUSED_ONE_PATH 1   // 1: every wave takes the wall-aware code (half the code, a select per point)
 #endif
+#ifndef IFD_SRF_D64
+#define IFD_SRF_D64 1   // FP32SRF: the non-equilibrium part e - g of stage A in FP64 (0: in FP32)
+#endif
 #ifndef IFD_FUSED_WAVES_F32
 #define IFD_FUSED_WAVES_F32 2
 #endif
@@ -475,7 +478,7 @@ struct March {
             const V lam_old = V(ln_);
             if (t + 1 <= t_last) fetch(t + 1);   // consumed by the next row
             V l;
-            if constexpr (S::kExactFinal) {
+            if constexpr (S::kExactFinal && IFD_SRF_D64) {
                 // e - g in FP64 from the exact stored g: at low shear the non-equilibrium part is far below
                 // an FP32 ulp of g, and Step (2) raises it to the power (n - 1) / 2
                 double gd[9], dd[9], Pd, uxd, uyd;

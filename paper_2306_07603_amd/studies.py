@@ -13,6 +13,8 @@ python -m paper_2306_07603_amd.studies <name> [--out FILE] [options]
   stress     a high-Reynolds stability check (theta = 45 deg, Re = 50 000).
   unsteady   the 1025 x 1025 unsteady case in FP16-deviation, FP32 and FP64
              storage: time-averaged |u| differences and throughput.
+  adjoint    the 129 x 129 gradient case: discrete adjoint (FP32SRF and FP64
+             trajectories), tangent sweep and central differences, timed.
 
 Every study prints one progress line per chunk of steps and writes a JSON
 summary.  Inputs are the paper's problem statement with seeded parameters; no
@@ -229,7 +231,47 @@ def unsteady(n_side: int = 1025, steps: int = 200000, average_from: int = 100000
     return out
 
 
-STUDIES = {"regime": regime, "precision": precision, "lag": lag, "stress": stress, "unsteady": unsteady}
+def adjoint(n_side: int = 129, steps: int = 20000, checkpoint_every: int = 500) -> dict:
+    """Gradient of the kinetic energy (Eq. 5.1) after `steps` steps, Re 400, n 0.7,
+    theta 60: the discrete adjoint (FP32SRF and FP64 trajectories), the tangent
+    sweep and central differences (h = 1e-4) of the FP64 forward, with times."""
+    import math
+    re, n, th, u = 400.0, 0.7, 60.0, 0.1
+    out = {"study": "adjoint", "n_side": n_side, "steps": steps, "checkpoint_every": checkpoint_every, "runs": {}}
+
+    def ke(theta_deg, nn, uu):
+        h = M.ifdlbm_create([M.Cavity(n_side, n_side, re, nn, theta_deg, uu)],
+                            M.ifdlbm_default_options(precision="fp64", graph_steps=1000, residual_every=1000))
+        M.ifdlbm_step(h, steps)
+        e = M.ifdlbm_kinetic_energy(h, 0)
+        h.close()
+        return e
+
+    t0 = time.time()
+    hh = 1e-4
+    fd = [(ke(th + math.degrees(hh), n, u) - ke(th - math.degrees(hh), n, u)) / (2 * hh),
+          (ke(th, n + hh, u) - ke(th, n - hh, u)) / (2 * hh),
+          (ke(th, n, u + hh * u) - ke(th, n, u - hh * u)) / (2 * hh * u)]
+    out["runs"]["central_differences"] = {"grad": fd, "seconds": time.time() - t0, "forward_runs": 6}
+    log("adjoint: central differences %s, %.1f s" % (["%.6e" % g for g in fd], time.time() - t0))
+    cav = M.Cavity(n_side, n_side, re, n, th, u)
+    for name, fn in (("adjoint_fp32srf", lambda: M.ifdlbm_adjoint(cav, M.ifdlbm_default_options(precision="fp32srf"),
+                                                                     steps, checkpoint_every)),
+                     ("adjoint_fp64", lambda: M.ifdlbm_adjoint(cav, M.ifdlbm_default_options(precision="fp64"),
+                                                                 steps, checkpoint_every)),
+                     ("tangent_fp64", lambda: M.ifdlbm_gradient(cav, M.ifdlbm_default_options(), steps))):
+        t0 = time.time()
+        J, g = fn()
+        dt = time.time() - t0
+        rel = [abs(g[q] - fd[q]) / abs(fd[q]) for q in range(3)]
+        out["runs"][name] = {"J": J, "grad": [float(x) for x in g], "seconds": dt, "rel_vs_fd": rel}
+        log("adjoint: %s J %.10e grad %s, rel to differences %s, %.1f s"
+            % (name, J, ["%.6e" % x for x in g], ["%.1e" % r for r in rel], dt))
+    return out
+
+
+STUDIES = {"regime": regime, "precision": precision, "lag": lag, "stress": stress, "unsteady": unsteady,
+           "adjoint": adjoint}
 
 
 def main(argv=None) -> int:
