@@ -153,7 +153,9 @@ int ifdlbm_sync(ifdlbm_t* h);
 int ifdlbm_run_to_steady(ifdlbm_t* h, double tol, int64_t max_steps,
                          int64_t* steps_done, double* res_u, double* res_p);
 
-/* Last evaluated residuals E(u), E(P) of Eq. (2.19) for every cavity (arrays of n_cav, caller-owned). */
+/* Last evaluated residuals E(u), E(P) of Eq. (2.19) for every cavity (arrays of n_cav, caller-owned).  A running
+   cavity whose residual sums are non-finite is marked IFDLBM_STATUS_DIVERGED here and stops stepping; the
+   others continue (its residuals read NaN). */
 int ifdlbm_get_residuals(ifdlbm_t* h, double* res_u, double* res_p);
 
 /* Velocity (u, v) and pressure P of Eqs. (2.10)-(2.11) of cavity cav, FP64, into caller-owned host

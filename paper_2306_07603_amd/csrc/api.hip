@@ -654,16 +654,25 @@ int ifdlbm_get_residuals(ifdlbm_t* h, double* res_u, double* res_p)
     std::vector<double> sums;
     int rc = read_residuals(h, sums);
     if (rc) return rc;
+    bool changed = false;
     for (int c = 0; c < h->n_cav; ++c) {
         if (h->desc[c].active) {
             double eu, ep;
             const bool ok = residuals_of(&sums[(size_t)c * kPartials], (double)h->desc[c].nx * h->desc[c].ny, eu, ep);
             h->res_u[c] = ok ? eu : NAN;
             h->res_p[c] = ok ? ep : NAN;
+            if (!ok) {   // non-finite state: the cavity stops stepping, the others continue
+                h->status[c] = IFDLBM_STATUS_DIVERGED;
+                h->desc[c].active = 0;
+                rc = mirror_state(h, c);
+                if (rc) return rc;
+                changed = true;
+            }
         }
         if (res_u) res_u[c] = h->res_u[c];
         if (res_p) res_p[c] = h->res_p[c];
     }
+    if (changed) return rebuild_worklists(h);
     return IFDLBM_OK;
 }
 

@@ -171,26 +171,37 @@ def lag(n_side: int = 65) -> dict:
     return out
 
 
+STRESS_VARIANTS = [("default (mix 0.5, CFL 0.5)", {}), ("central stencil (mix 1)", {"mix": 1.0}),
+                   ("mix 0.75", {"mix": 0.75}), ("CFL 0.25", {"cfl": 0.25})]
+
+
 def stress(n_side: int = 129, time_units: float = 500.0) -> dict:
     """theta = 45 deg, Re = 50 000 on 129 x 129 (Newtonian and two power
-    laws): does the run stay finite?"""
+    laws) for `time_units`: does the run stay finite?  Repeated with the
+    options the paper leaves open (the mixing weight of Eq. 2.5, the CFL)."""
     specs = [(45.0, 1.0, 50000.0), (45.0, 0.8, 50000.0), (45.0, 1.2, 50000.0)]
     cav = [M.Cavity(n_side, n_side, re, n, th, 0.1) for th, n, re in specs]
-    h = M.ifdlbm_create(cav, M.ifdlbm_default_options(precision="fp64", residual_every=1000, graph_steps=1000))
-    steps = int(time_units / min(M.ifdlbm_time_step(h, c) for c in range(len(cav)))) // 1000 * 1000
-    t0 = time.time()
-    for k in range(0, steps, 100000):
-        M.ifdlbm_step(h, min(100000, steps - k))
-        M.ifdlbm_sync(h)
-        log("stress: %d / %d steps, %.0f s" % (min(k + 100000, steps), steps, time.time() - t0))
-    res = M.ifdlbm_get_residuals(h)
-    out = {"study": "stress", "n_side": n_side, "steps": steps, "cases": []}
-    for c, (th, n, re) in enumerate(specs):
-        u, v, _ = M.ifdlbm_get_fields(h, c)
-        finite = bool(np.all(np.isfinite(u)) and np.all(np.isfinite(v)))
-        out["cases"].append({"theta": th, "n": n, "re": re, "finite": finite, "status": M.ifdlbm_status(h, c),
-                             "res_u": float(res[0][c]), "max_speed": float(np.hypot(u, v).max()) if finite else None})
-        log("stress: theta %g n %g Re %g finite %s" % (th, n, re, finite))
+    out = {"study": "stress", "n_side": n_side, "time_units": time_units, "variants": []}
+    for label, opt in STRESS_VARIANTS:
+        h = M.ifdlbm_create(cav, M.ifdlbm_default_options(precision="fp64", residual_every=1000, graph_steps=1000,
+                                                          **opt))
+        steps = int(time_units / min(M.ifdlbm_time_step(h, c) for c in range(len(cav)))) // 1000 * 1000
+        t0 = time.time()
+        for k in range(0, steps, 100000):
+            M.ifdlbm_step(h, min(100000, steps - k))
+            M.ifdlbm_sync(h)
+            log("stress %s: %d / %d steps, %.0f s" % (label, min(k + 100000, steps), steps, time.time() - t0))
+        res = M.ifdlbm_get_residuals(h)
+        cases = []
+        for c, (th, n, re) in enumerate(specs):
+            u, v, _ = M.ifdlbm_get_fields(h, c)
+            finite = bool(np.all(np.isfinite(u)) and np.all(np.isfinite(v)))
+            cases.append({"theta": th, "n": n, "re": re, "finite": finite, "status": M.ifdlbm_status(h, c),
+                          "res_u": float(res[0][c]), "max_speed": float(np.hypot(u, v).max()) if finite else None})
+            log("stress %s: theta %g n %g Re %g finite %s, E(u) %.2e"
+                % (label, th, n, re, finite, res[0][c]))
+        out["variants"].append({"label": label, "options": opt, "steps": steps, "cases": cases})
+        h.close()
     return out
 
 
