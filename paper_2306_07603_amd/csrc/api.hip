@@ -22,11 +22,25 @@ thread_local std::string g_last_error;
 // Records the text of the last error of this thread and returns code.
 int fail(int code, const std::string& msg)
 {
-    g_last_error = msg;
+    try {
+        g_last_error = msg;
+    } catch (...) {
+    }
     return code;
 }
 
 }  // namespace ifd
+
+// Body of a C entry point: a host allocation failure (or any other C++
+// exception) becomes an error code instead of crossing the C ABI.
+#define IFD_GUARD(call)                                                       \
+    try {                                                                     \
+        return call;                                                          \
+    } catch (const std::bad_alloc&) {                                         \
+        return fail(IFDLBM_ENOMEM, "host memory allocation failed");          \
+    } catch (...) {                                                           \
+        return fail(IFDLBM_EDEVICE, "unexpected C++ exception in the library"); \
+    }
 
 namespace {
 
@@ -472,7 +486,7 @@ int ifdlbm_default_options(ifdlbm_options* opt)
     return IFDLBM_OK;
 }
 
-int ifdlbm_create(const ifdlbm_cavity* cav, int32_t n_cav, const ifdlbm_options* opt, ifdlbm_t** out)
+static int ifdlbm_create_impl(const ifdlbm_cavity* cav, int32_t n_cav, const ifdlbm_options* opt, ifdlbm_t** out)
 {
     if (!out) return fail(IFDLBM_EINVAL, "null output handle pointer");
     *out = nullptr;
@@ -634,21 +648,21 @@ int ifdlbm_create(const ifdlbm_cavity* cav, int32_t n_cav, const ifdlbm_options*
     return IFDLBM_OK;
 }
 
-int ifdlbm_step(ifdlbm_t* h, int64_t n_steps)
+static int ifdlbm_step_impl(ifdlbm_t* h, int64_t n_steps)
 {
     if (!h) return fail(IFDLBM_EINVAL, "null handle");
     if (n_steps < 0) return fail(IFDLBM_EINVAL, "n_steps must be >= 0");
     return do_steps(h, n_steps);
 }
 
-int ifdlbm_sync(ifdlbm_t* h)
+static int ifdlbm_sync_impl(ifdlbm_t* h)
 {
     if (!h) return fail(IFDLBM_EINVAL, "null handle");
     IFD_HIP(hipStreamSynchronize(h->stream));
     return IFDLBM_OK;
 }
 
-int ifdlbm_get_residuals(ifdlbm_t* h, double* res_u, double* res_p)
+static int ifdlbm_get_residuals_impl(ifdlbm_t* h, double* res_u, double* res_p)
 {
     if (!h) return fail(IFDLBM_EINVAL, "null handle");
     std::vector<double> sums;
@@ -676,7 +690,7 @@ int ifdlbm_get_residuals(ifdlbm_t* h, double* res_u, double* res_p)
     return IFDLBM_OK;
 }
 
-int ifdlbm_run_to_steady(ifdlbm_t* h, double tol, int64_t max_steps, int64_t* steps_done, double* res_u, double* res_p)
+static int ifdlbm_run_to_steady_impl(ifdlbm_t* h, double tol, int64_t max_steps, int64_t* steps_done, double* res_u, double* res_p)
 {
     if (!h) return fail(IFDLBM_EINVAL, "null handle");
     if (!(tol >= 0.0) || max_steps < 0) return fail(IFDLBM_EINVAL, "tol must be >= 0 and max_steps >= 0");
@@ -743,7 +757,7 @@ int ifdlbm_run_to_steady(ifdlbm_t* h, double tol, int64_t max_steps, int64_t* st
     return IFDLBM_OK;
 }
 
-int ifdlbm_get_fields_device(ifdlbm_t* h, int32_t cav, void* u, void* v, void* p, int32_t dtype)
+static int ifdlbm_get_fields_device_impl(ifdlbm_t* h, int32_t cav, void* u, void* v, void* p, int32_t dtype)
 {
     int rc = check_cav(h, cav);
     if (rc) return rc;
@@ -753,7 +767,7 @@ int ifdlbm_get_fields_device(ifdlbm_t* h, int32_t cav, void* u, void* v, void* p
     return IFDLBM_OK;
 }
 
-int ifdlbm_get_fields(ifdlbm_t* h, int32_t cav, double* u, double* v, double* p)
+static int ifdlbm_get_fields_impl(ifdlbm_t* h, int32_t cav, double* u, double* v, double* p)
 {
     int rc = check_cav(h, cav);
     if (rc) return rc;
@@ -769,7 +783,7 @@ int ifdlbm_get_fields(ifdlbm_t* h, int32_t cav, double* u, double* v, double* p)
     return IFDLBM_OK;
 }
 
-int ifdlbm_kinetic_energy(ifdlbm_t* h, int32_t cav, double* energy)
+static int ifdlbm_kinetic_energy_impl(ifdlbm_t* h, int32_t cav, double* energy)
 {
     int rc = check_cav(h, cav);
     if (rc) return rc;
@@ -787,7 +801,7 @@ int ifdlbm_kinetic_energy(ifdlbm_t* h, int32_t cav, double* energy)
     return IFDLBM_OK;
 }
 
-int ifdlbm_get_state(ifdlbm_t* h, int32_t cav, double* fhat, double* lambda)
+static int ifdlbm_get_state_impl(ifdlbm_t* h, int32_t cav, double* fhat, double* lambda)
 {
     int rc = check_cav(h, cav);
     if (rc) return rc;
@@ -803,7 +817,7 @@ int ifdlbm_get_state(ifdlbm_t* h, int32_t cav, double* fhat, double* lambda)
     return IFDLBM_OK;
 }
 
-int ifdlbm_set_state(ifdlbm_t* h, int32_t cav, const double* fhat, const double* lambda)
+static int ifdlbm_set_state_impl(ifdlbm_t* h, int32_t cav, const double* fhat, const double* lambda)
 {
     int rc = check_cav(h, cav);
     if (rc) return rc;
@@ -827,14 +841,14 @@ int ifdlbm_set_state(ifdlbm_t* h, int32_t cav, const double* fhat, const double*
     return IFDLBM_OK;
 }
 
-int ifdlbm_status(ifdlbm_t* h, int32_t cav)
+static int ifdlbm_status_impl(ifdlbm_t* h, int32_t cav)
 {
     int rc = check_cav(h, cav);
     if (rc) return rc;
     return h->status[cav];
 }
 
-int ifdlbm_autotune(ifdlbm_t* h, int32_t steps_per_trial, int32_t* segment_rows, double* ms_per_step)
+static int ifdlbm_autotune_impl(ifdlbm_t* h, int32_t steps_per_trial, int32_t* segment_rows, double* ms_per_step)
 {
     if (!h) return fail(IFDLBM_EINVAL, "null handle");
     if (steps_per_trial < 1 || steps_per_trial > 10000) return fail(IFDLBM_EINVAL, "steps_per_trial must be in [1, 10000]");
@@ -913,7 +927,7 @@ int ifdlbm_autotune(ifdlbm_t* h, int32_t steps_per_trial, int32_t* segment_rows,
     return IFDLBM_OK;
 }
 
-int ifdlbm_info(ifdlbm_t* h, ifdlbm_info_t* info)
+static int ifdlbm_info_impl(ifdlbm_t* h, ifdlbm_info_t* info)
 {
     if (!h || !info) return fail(IFDLBM_EINVAL, "null argument");
     std::memset(info, 0, sizeof(*info));
@@ -933,7 +947,7 @@ int ifdlbm_info(ifdlbm_t* h, ifdlbm_info_t* info)
     return IFDLBM_OK;
 }
 
-int ifdlbm_gradient(const ifdlbm_cavity* cav, const ifdlbm_options* opt, int64_t n_steps, int32_t objective, double* J,
+static int ifdlbm_gradient_impl(const ifdlbm_cavity* cav, const ifdlbm_options* opt, int64_t n_steps, int32_t objective, double* J,
                     double grad[3])
 {
     if (!cav || !opt || !J || !grad) return fail(IFDLBM_EINVAL, "null argument");
@@ -965,13 +979,15 @@ int ifdlbm_gradient(const ifdlbm_cavity* cav, const ifdlbm_options* opt, int64_t
     return IFDLBM_OK;
 }
 
-int ifdlbm_adjoint(const ifdlbm_cavity* cav, const ifdlbm_options* opt, int64_t n_steps, int32_t checkpoint_every,
+static int ifdlbm_adjoint_impl(const ifdlbm_cavity* cav, const ifdlbm_options* opt, int64_t n_steps, int32_t checkpoint_every,
                    int32_t objective, double* J, double grad[3])
 {
     if (!cav || !opt || !J || !grad) return fail(IFDLBM_EINVAL, "null argument");
     if (objective != IFDLBM_OBJ_KINETIC_ENERGY) return fail(IFDLBM_EINVAL, "unknown objective");
     if (n_steps < 1) return fail(IFDLBM_EINVAL, "n_steps must be >= 1");
     if (checkpoint_every < 1) return fail(IFDLBM_EINVAL, "checkpoint_every must be >= 1");
+    if ((n_steps + checkpoint_every - 1) / checkpoint_every > ((int64_t)1 << 24))
+        return fail(IFDLBM_EINVAL, "more than 2^24 checkpoints: raise checkpoint_every");
     if (opt->lambda_mode != IFDLBM_LAMBDA_LAGGED)
         return fail(IFDLBM_EINVAL, "the adjoint follows the lagged lambda of Step (2)");
     ifdlbm_options o = *opt;
@@ -1060,7 +1076,7 @@ int ifdlbm_adjoint(const ifdlbm_cavity* cav, const ifdlbm_options* opt, int64_t 
     return rc;
 }
 
-int ifdlbm_record(ifdlbm_t* h, int32_t every, int32_t capacity)
+static int ifdlbm_record_impl(ifdlbm_t* h, int32_t every, int32_t capacity)
 {
     if (!h) return fail(IFDLBM_EINVAL, "null handle");
     if (every < 0) return fail(IFDLBM_EINVAL, "every must be >= 0");
@@ -1092,7 +1108,7 @@ int ifdlbm_record(ifdlbm_t* h, int32_t every, int32_t capacity)
     return IFDLBM_OK;
 }
 
-int ifdlbm_get_record(ifdlbm_t* h, int32_t cav, int32_t max_samples, int32_t* n, int64_t* steps, double* u, double* v,
+static int ifdlbm_get_record_impl(ifdlbm_t* h, int32_t cav, int32_t max_samples, int32_t* n, int64_t* steps, double* u, double* v,
                       double* ke)
 {
     int rc = check_cav(h, cav);
@@ -1121,7 +1137,7 @@ int ifdlbm_get_record(ifdlbm_t* h, int32_t cav, int32_t max_samples, int32_t* n,
     return IFDLBM_OK;
 }
 
-int ifdlbm_time_step(ifdlbm_t* h, int32_t cav, double* dt)
+static int ifdlbm_time_step_impl(ifdlbm_t* h, int32_t cav, double* dt)
 {
     int rc = check_cav(h, cav);
     if (rc) return rc;
@@ -1132,10 +1148,13 @@ int ifdlbm_time_step(ifdlbm_t* h, int32_t cav, double* dt)
 
 void ifdlbm_destroy(ifdlbm_t* h)
 {
-    if (!h) return;
-    if (h->stream) (void)hipStreamSynchronize(h->stream);
-    free_all(h);
-    delete h;
+    try {
+        if (!h) return;
+        if (h->stream) (void)hipStreamSynchronize(h->stream);
+        free_all(h);
+        delete h;
+    } catch (...) {
+    }
 }
 
 const char* ifdlbm_strerror(int code)
@@ -1152,5 +1171,100 @@ const char* ifdlbm_strerror(int code)
 }
 
 const char* ifdlbm_last_error(void) { return g_last_error.c_str(); }
+
+
+// C entry points: no C++ exception crosses the ABI.
+int ifdlbm_create(const ifdlbm_cavity* cav, int32_t n_cav, const ifdlbm_options* opt, ifdlbm_t** out)
+{
+    IFD_GUARD(ifdlbm_create_impl(cav, n_cav, opt, out));
+}
+
+int ifdlbm_step(ifdlbm_t* h, int64_t n_steps)
+{
+    IFD_GUARD(ifdlbm_step_impl(h, n_steps));
+}
+
+int ifdlbm_sync(ifdlbm_t* h)
+{
+    IFD_GUARD(ifdlbm_sync_impl(h));
+}
+
+int ifdlbm_get_residuals(ifdlbm_t* h, double* res_u, double* res_p)
+{
+    IFD_GUARD(ifdlbm_get_residuals_impl(h, res_u, res_p));
+}
+
+int ifdlbm_run_to_steady(ifdlbm_t* h, double tol, int64_t max_steps, int64_t* steps_done, double* res_u, double* res_p)
+{
+    IFD_GUARD(ifdlbm_run_to_steady_impl(h, tol, max_steps, steps_done, res_u, res_p));
+}
+
+int ifdlbm_get_fields_device(ifdlbm_t* h, int32_t cav, void* u, void* v, void* p, int32_t dtype)
+{
+    IFD_GUARD(ifdlbm_get_fields_device_impl(h, cav, u, v, p, dtype));
+}
+
+int ifdlbm_get_fields(ifdlbm_t* h, int32_t cav, double* u, double* v, double* p)
+{
+    IFD_GUARD(ifdlbm_get_fields_impl(h, cav, u, v, p));
+}
+
+int ifdlbm_kinetic_energy(ifdlbm_t* h, int32_t cav, double* energy)
+{
+    IFD_GUARD(ifdlbm_kinetic_energy_impl(h, cav, energy));
+}
+
+int ifdlbm_get_state(ifdlbm_t* h, int32_t cav, double* fhat, double* lambda)
+{
+    IFD_GUARD(ifdlbm_get_state_impl(h, cav, fhat, lambda));
+}
+
+int ifdlbm_set_state(ifdlbm_t* h, int32_t cav, const double* fhat, const double* lambda)
+{
+    IFD_GUARD(ifdlbm_set_state_impl(h, cav, fhat, lambda));
+}
+
+int ifdlbm_status(ifdlbm_t* h, int32_t cav)
+{
+    IFD_GUARD(ifdlbm_status_impl(h, cav));
+}
+
+int ifdlbm_autotune(ifdlbm_t* h, int32_t steps_per_trial, int32_t* segment_rows, double* ms_per_step)
+{
+    IFD_GUARD(ifdlbm_autotune_impl(h, steps_per_trial, segment_rows, ms_per_step));
+}
+
+int ifdlbm_info(ifdlbm_t* h, ifdlbm_info_t* info)
+{
+    IFD_GUARD(ifdlbm_info_impl(h, info));
+}
+
+int ifdlbm_gradient(const ifdlbm_cavity* cav, const ifdlbm_options* opt, int64_t n_steps, int32_t objective, double* J,
+                    double grad[3])
+{
+    IFD_GUARD(ifdlbm_gradient_impl(cav, opt, n_steps, objective, J, grad));
+}
+
+int ifdlbm_adjoint(const ifdlbm_cavity* cav, const ifdlbm_options* opt, int64_t n_steps, int32_t checkpoint_every,
+                   int32_t objective, double* J, double grad[3])
+{
+    IFD_GUARD(ifdlbm_adjoint_impl(cav, opt, n_steps, checkpoint_every, objective, J, grad));
+}
+
+int ifdlbm_record(ifdlbm_t* h, int32_t every, int32_t capacity)
+{
+    IFD_GUARD(ifdlbm_record_impl(h, every, capacity));
+}
+
+int ifdlbm_get_record(ifdlbm_t* h, int32_t cav, int32_t max_samples, int32_t* n, int64_t* steps, double* u, double* v,
+                      double* ke)
+{
+    IFD_GUARD(ifdlbm_get_record_impl(h, cav, max_samples, n, steps, u, v, ke));
+}
+
+int ifdlbm_time_step(ifdlbm_t* h, int32_t cav, double* dt)
+{
+    IFD_GUARD(ifdlbm_time_step_impl(h, cav, dt));
+}
 
 }  // extern "C"

@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -66,7 +67,9 @@ double refine(const std::vector<double>& P, size_t k)
 
 }  // namespace
 
-extern "C" int ifdlbm_classify(const double* x, int64_t n, double dt_sample, double steady_tol, ifdlbm_regime_t* out)
+namespace {
+
+int classify(const double* x, int64_t n, double dt_sample, double steady_tol, ifdlbm_regime_t* out)
 {
     using ifd::fail;
     if (!x || !out) return fail(IFDLBM_EINVAL, "null series or output");
@@ -150,4 +153,17 @@ extern "C" int ifdlbm_classify(const double* x, int64_t n, double dt_sample, dou
         r.regime = IFDLBM_REGIME_APERIODIC;
     *out = r;
     return IFDLBM_OK;
+}
+
+}  // namespace
+
+extern "C" int ifdlbm_classify(const double* x, int64_t n, double dt_sample, double steady_tol, ifdlbm_regime_t* out)
+{
+    try {
+        return classify(x, n, dt_sample, steady_tol, out);
+    } catch (const std::bad_alloc&) {
+        return ifd::fail(IFDLBM_ENOMEM, "host memory allocation failed");
+    } catch (...) {
+        return ifd::fail(IFDLBM_EDEVICE, "unexpected C++ exception in the library");
+    }
 }

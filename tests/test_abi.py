@@ -96,6 +96,7 @@ def test_gradient_calls_reject_bad_arguments():
     calls = [
         lambda: M.ifdlbm_adjoint(cav, o, 0, 10),
         lambda: M.ifdlbm_adjoint(cav, o, 10, 0),
+        lambda: M.ifdlbm_adjoint(cav, o, 1 << 40, 1),   # more than 2^24 checkpoints
         lambda: M.ifdlbm_adjoint(cav, o, 10, 5, objective=3),
         lambda: M.ifdlbm_adjoint(cav, M.ifdlbm_default_options(lambda_mode=M.IFDLBM_LAMBDA_IMPLICIT), 10, 5),
         lambda: M.ifdlbm_adjoint(M.Cavity(4, 17, 100.0, 0.8, 60.0), o, 10, 5),
