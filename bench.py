@@ -183,9 +183,12 @@ def main() -> int:
     wall, ev_ms = time_steps(M, h, stream, args.steps, args.warmup)
     ru, rp = M.ifdlbm_get_residuals(h)
     import numpy as np
-    diverged = int(np.sum(~(np.isfinite(ru) & np.isfinite(rp))))
+    bad = [int(c) for c in np.nonzero(~(np.isfinite(ru) & np.isfinite(rp)))[0]]
+    diverged = len(bad)
     if diverged:
-        log("WARNING: %d cavities have non-finite residuals" % diverged)
+        log("WARNING: %d cavities have non-finite residuals: %s" % (diverged, ", ".join(
+            "%d (side %d, Re %.0f, n %.3f, theta %.2f)" % (c, specs[c].n_xi, specs[c].re, specs[c].n, specs[c].theta_deg)
+            for c in bad)))
     nodes = info["nodes"]
     mlups = nodes * args.steps / wall / 1e6
     launches = args.steps * info["launches_per_step"]
@@ -239,7 +242,7 @@ def main() -> int:
         "dtype": PRECISION[args.precision][1], "data": "synthetic",
         "config": {"workload": WORKLOAD, "cavities": len(specs), "nodes_per_step": nodes, "kernel": args.kernel,
                    "precision": args.precision, "storage": PRECISION[args.precision][0],
-                   "diverged_cavities": diverged,
+                   "diverged_cavities": diverged, "diverged_indices": bad,
                    "residual_every": args.residual_every, "graph_steps": args.graph_steps,
                    "segment_rows": seg_rows, "autotune_steps": args.autotune_steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -156,7 +156,7 @@ template <> struct Storage<P_FP32SR> {
     using V = float;
     __device__ static inline T cvt(F v, int) { return (T)v; }
     __device__ static inline F enc(T v, int) { return (F)v; }
-    __device__ static inline F enc_sr(T v, uint32_t r16) { return round_stochastic(v, r16); }
+    __device__ static inline F enc_sr(T v, int, uint32_t r16) { return round_stochastic(v, r16); }
     __device__ static inline T load(const F* p, int64_t i, int k) { return cvt(p[i], k); }
     __device__ static inline void store(F* p, int64_t i, int k, T v) { p[i] = enc(v, k); }
 };
@@ -176,7 +176,7 @@ template <> struct Storage<P_FP32SRF> {
     using V = float;
     __device__ static inline T cvt(F v, int) { return v; }
     __device__ static inline F enc(T v, int) { return v; }
-    __device__ static inline F enc_sr(double v, uint32_t r16) { return round_stochastic(v, r16); }
+    __device__ static inline F enc_sr(double v, int, uint32_t r16) { return round_stochastic(v, r16); }
     __device__ static inline T load(const F* p, int64_t i, int k) { return cvt(p[i], k); }
     __device__ static inline void store(F* p, int64_t i, int k, T v) { p[i] = enc(v, k); }
 };
@@ -186,15 +186,18 @@ template <typename S, typename X>
 __device__ __forceinline__ typename S::F encode_state(X v, int k, const NodeWords* nw)
 {
     if constexpr (S::kStochastic)
-        return S::enc_sr(v, nw->r16(k));
+        return S::enc_sr(v, k, nw->r16(k));
     else
         return S::enc(v, k);
 }
 
 // FP16 storage of g_k / omega_k: the division by the lattice weight puts all
 // nine planes on the same O(3 P + 3 c.u) scale, inside FP16's normal range.
+// New states are rounded stochastically: on fine grids the change of a
+// population per step is far below an FP16 ulp (2^-11 relative), and round to
+// nearest would drop it every step.
 template <> struct Storage<P_FP16DEV> {
-    static constexpr bool kStochastic = false;
+    static constexpr bool kStochastic = true;
     static constexpr bool kExactFinal = false;
     using F = __half;
     using L = float;
@@ -204,6 +207,17 @@ template <> struct Storage<P_FP16DEV> {
     __device__ static inline float inv_w(int k) { return k == 0 ? 2.25f : (k < 5 ? 9.0f : 36.0f); }
     __device__ static inline T cvt(F v, int k) { return w(k) * __half2float(v); }
     __device__ static inline F enc(T v, int k) { return __float2half_rn(v * inv_w(k)); }
+    // The 13 significand bits of the FP32 value below FP16's are added to 13
+    // random bits and dropped: the kept value rounds up with probability equal
+    // to the dropped fraction.  Below FP16's normal range (|x| < 2^-14) the
+    // final conversion rounds to nearest on the subnormal grid.
+    __device__ static inline F enc_sr(T v, int k, uint32_t r16)
+    {
+        const float x = v * inv_w(k);
+        const uint32_t b = __float_as_uint(x);
+        if ((b & 0x7F800000u) == 0x7F800000u) return __float2half_rn(x);   // inf, nan
+        return __float2half_rn(__uint_as_float((b + (r16 >> 3)) & ~0x1FFFu));
+    }
     __device__ static inline T load(const F* p, int64_t i, int k) { return cvt(p[i], k); }
     __device__ static inline void store(F* p, int64_t i, int k, T v) { p[i] = enc(v, k); }
 };

@@ -3,15 +3,19 @@
 // arXiv:2306.07603, read from the velocity at the cavity centre or the
 // kinetic energy of Eq. (5.1)).
 //
-// Method: remove the mean; a relative fluctuation amplitude at or below the
-// tolerance is a steady state.  Otherwise Hann-window the series, zero-pad it
-// to a power of two at least four times its length, take the power spectrum
-// with an iterative radix-2 Cooley-Tukey FFT, and locate the strongest peak
-// (frequency refined by a parabola through the logarithms of the three bins
-// around it).  The share of the spectral energy within the main lobe of that
-// frequency and of its integer multiples decides "periodic"; otherwise a
-// second narrow peak away from those multiples that holds most of the rest
-// decides "quasi-periodic"; anything else is "aperiodic".
+// Method: a relative fluctuation amplitude at or below the tolerance is a
+// steady state.  Otherwise remove the least-squares line (mean and drift),
+// Hann-window the series, zero-pad it to a power of two at least four times its
+// length, take the power spectrum with an iterative radix-2 Cooley-Tukey FFT,
+// and locate the strongest spectral peak above 1.5 cycles per record: a bin
+// that is a local maximum (frequency refined by a parabola through the
+// logarithms of the three bins around it).  The share of the whole
+// fluctuation energy within the main lobe of the peak frequency and of its
+// integer multiples decides "periodic"; otherwise a second narrow peak away
+// from those multiples that holds most of the rest decides "quasi-periodic";
+// anything else is "aperiodic".  A series still relaxing (a drift that is not
+// a straight line, or a period longer than the record) keeps most of its
+// energy below 1.5 cycles per record and is therefore "aperiodic".
 #include "ifdlbm.h"
 
 #include <algorithm>
@@ -94,12 +98,20 @@ int classify(const double* x, int64_t n, double dt_sample, double steady_tol, if
         *out = r;
         return IFDLBM_OK;
     }
+    // least-squares line through the series, about its centre
+    const double tc = 0.5 * (double)(n - 1);
+    double stx = 0.0, stt = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        stx += ((double)i - tc) * (x[i] - mean);
+        stt += ((double)i - tc) * ((double)i - tc);
+    }
+    const double slope = stx / stt;
     size_t N = 1;
     while (N < (size_t)n * kPad) N <<= 1;
     std::vector<std::complex<double>> a(N, 0.0);
     for (int64_t i = 0; i < n; ++i) {
         const double w = 0.5 - 0.5 * std::cos(2.0 * M_PI * (double)i / (double)(n - 1));
-        a[(size_t)i] = (x[i] - mean) * w;
+        a[(size_t)i] = (x[i] - mean - slope * ((double)i - tc)) * w;
     }
     fft(a);
     std::vector<double> P(N / 2 + 1);
@@ -107,13 +119,14 @@ int classify(const double* x, int64_t n, double dt_sample, double steady_tol, if
     // bins below 1.5 cycles per record carry the window's leakage of the mean and trends
     const size_t k_lo = (size_t)std::ceil(1.5 * (double)N / (double)n);
     const double lobe = 2.0 * (double)N / (double)n;   // Hann main-lobe half width, in bins
+    // shares are taken of the whole fluctuation spectrum, so that energy below
+    // 1.5 cycles per record (an unfinished transient) counts against a peak
     double total = 0.0;
-    size_t k1 = k_lo;
-    for (size_t k = k_lo; k < P.size(); ++k) {
-        total += P[k];
-        if (P[k] > P[k1]) k1 = k;
-    }
-    if (!(total > 0.0) || k_lo >= P.size()) {
+    for (size_t k = 1; k < P.size(); ++k) total += P[k];
+    size_t k1 = 0;   // strongest local maximum strictly above k_lo
+    for (size_t k = k_lo + 1; k + 1 < P.size(); ++k)
+        if (P[k] >= P[k - 1] && P[k] >= P[k + 1] && (k1 == 0 || P[k] > P[k1])) k1 = k;
+    if (!(total > 0.0) || k_lo >= P.size() || k1 == 0) {
         r.regime = IFDLBM_REGIME_APERIODIC;
         *out = r;
         return IFDLBM_OK;

@@ -52,3 +52,19 @@ def test_classify_rejects_bad_input(x, dt):
     with pytest.raises(M.IfdlbmError) as e:
         M.ifdlbm_classify(x, dt)
     assert e.value.code == M.IFDLBM_EINVAL
+
+
+def test_periodic_on_a_drift_is_periodic():
+    f = 0.0137
+    x = 0.3 + 2e-5 * T + 0.01 * np.sin(2 * np.pi * f * T)
+    r = M.ifdlbm_classify(x, DT)
+    assert r["name"] == "periodic", r
+    assert abs(r["f_main"] - f) <= 2e-3 * f, r
+
+
+def test_decaying_transient_is_not_periodic():
+    """A relaxation still under way (slow exponential plus a period longer
+    than the record) has no spectral peak above 1.5 cycles per record."""
+    x = 0.02 + 0.005 * np.exp(-T / 700.0) + 0.002 * np.sin(2 * np.pi * T / 2600.0)
+    r = M.ifdlbm_classify(x, DT)
+    assert r["name"] == "aperiodic", r
