@@ -60,7 +60,7 @@ def to_steady(h, tol: float, max_steps: int, chunk: int = 100000, label: str = "
             return rc == M.IFDLBM_OK, total, ru, rp
 
 
-def regime(n_side: int = 257, time_units: float = 3000.0, every: int = 50, precision: str = "fp32sr",
+def regime(n_side: int = 257, time_units: float = 3000.0, every: int = 50, precision: str = "fp32srf",
            chunk: int = 100000, steady_tol: float = 1e-4) -> dict:
     """Run every case of PAPER_REGIMES for `time_units` (lid speed 0.1, height
     1), record every `every` steps, classify the second half of the record."""
@@ -80,20 +80,22 @@ def regime(n_side: int = 257, time_units: float = 3000.0, every: int = 50, preci
         M.ifdlbm_sync(h)
         done += k
         log("regime: %d / %d steps, %.0f s" % (done, steps, time.time() - t0))
+    ru, _ = M.ifdlbm_get_residuals(h)
     out = []
     for c, (th, n, re, paper) in enumerate(PAPER_REGIMES):
         st, u, v, ke = M.ifdlbm_get_record(h, c, cap)
         half = st.size // 2
         dt_sample = every * dts[c]
         rk = M.ifdlbm_classify(ke[half:], dt_sample, steady_tol) if np.all(np.isfinite(ke[half:])) else None
-        ru = M.ifdlbm_classify(u[half:], dt_sample, steady_tol) if np.all(np.isfinite(u[half:])) else None
+        rc_ = M.ifdlbm_classify(u[half:], dt_sample, steady_tol) if np.all(np.isfinite(u[half:])) else None
         out.append({"theta": th, "n": n, "re": re, "paper": paper, "status": M.ifdlbm_status(h, c),
                     "time_units": float(st[-1] * dts[c]) if st.size else 0.0,
-                    "ke": rk, "u_centre": ru, "u_last": float(u[-1]) if u.size else None,
-                    "v_last": float(v[-1]) if v.size else None})
-        log("theta %g n %.1f Re %g: paper %s, ke %s (f %.4g), u %s (f %.4g)"
+                    "ke": rk, "u_centre": rc_, "u_last": float(u[-1]) if u.size else None,
+                    "v_last": float(v[-1]) if v.size else None, "res_u_final": float(ru[c])})
+        log("theta %g n %.1f Re %g: paper %s, ke %s (f %.4g, harm %.2f), u %s (f %.4g), E(u) %.1e"
             % (th, n, re, paper, rk["name"] if rk else "non-finite", rk["f_main"] if rk else 0,
-               ru["name"] if ru else "non-finite", ru["f_main"] if ru else 0))
+               rk["harmonic_fraction"] if rk else 0, rc_["name"] if rc_ else "non-finite",
+               rc_["f_main"] if rc_ else 0, ru[c]))
     return {"study": "regime", "n_side": n_side, "time_units": time_units, "every": every, "precision": precision,
             "steady_tol": steady_tol, "steps": steps, "seconds": time.time() - t0, "cases": out}
 
