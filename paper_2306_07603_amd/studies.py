@@ -209,13 +209,13 @@ def stress(n_side: int = 129, time_units: float = 500.0) -> dict:
 
 def unsteady(n_side: int = 1025, steps: int = 200000, average_from: int = 100000, every: int = 1000) -> dict:
     """theta = 75 deg, n = 1.2, Re = 1e4 on 1025 x 1025 in FP16-deviation, FP32
-    (stochastic rounding) and FP64 storage: time average of |u| over steps
+    (stochastic rounding, FP32 and FP64 arithmetic) and FP64 storage: time average of |u| over steps
     [average_from, steps) sampled every `every` steps, and throughput."""
     cav = [M.Cavity(n_side, n_side, 1e4, 1.2, 75.0, 0.1)]
     out = {"study": "unsteady", "n_side": n_side, "steps": steps, "average_from": average_from, "every": every,
            "runs": {}}
     means = {}
-    for prec in ("fp16dev", "fp32sr", "fp64"):
+    for prec in ("fp16dev", "fp32srf", "fp32sr", "fp64"):
         h = M.ifdlbm_create(cav, M.ifdlbm_default_options(precision=prec, residual_every=1000, graph_steps=1000))
         t0 = time.time()
         acc, nacc = None, 0
@@ -237,7 +237,7 @@ def unsteady(n_side: int = 1025, steps: int = 200000, average_from: int = 100000
                              "mlups_with_sampling": n_side * n_side * steps / wall / 1e6}
         h.close()
     ref = means["fp64"]
-    for prec in ("fp16dev", "fp32sr"):
+    for prec in ("fp16dev", "fp32srf", "fp32sr"):
         out["runs"][prec]["mean_speed_rel_diff_vs_fp64"] = float(np.abs(means[prec] - ref).max() / ref.max())
         log("unsteady %s: time-averaged |u| max relative difference to FP64 %.2e"
             % (prec, out["runs"][prec]["mean_speed_rel_diff_vs_fp64"]))
