@@ -113,7 +113,14 @@ def cpu_baseline(specs, steps: int):
         O.run(p, F, L, steps)
         nodes += s.n_xi * s.n_eta * steps
     dt = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": nodes / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "cpu_model": model, "host_cpus": os.cpu_count(),
             "sample": "serial FP64 oracle, %d steps of one cavity of each side (65, 129, 257, 513) of the batch, "
                       "%.1f s" % (steps, dt)}
 
@@ -144,6 +151,8 @@ def main() -> int:
     ap.add_argument("--graph-steps", type=int, default=100)
     ap.add_argument("--autotune-steps", type=int, default=10,
                     help="steps per trial of the segment-length autotuner before timing (0: automatic choice)")
+    ap.add_argument("--segment-rows", type=int, default=0,
+                    help="force the fused kernel's row-segment length (skips the autotuner; for profiling runs)")
     ap.add_argument("--plain-steps", type=int, default=100, help="steps of the plain FP64 comparison run (0: skip)")
     ap.add_argument("--other-steps", type=int, default=300,
                     help="steps of each other FP32-storage mode, reported beside the headline (0: skip)")
@@ -172,10 +181,11 @@ def main() -> int:
     cav = [M.Cavity(**s.__dict__) for s in specs]
 
     opt = M.ifdlbm_default_options(precision=args.precision, kernel=args.kernel, residual_every=args.residual_every,
-                                   graph_steps=args.graph_steps, batched=1, hip_stream=stream.cuda_stream)
+                                   graph_steps=args.graph_steps, batched=1, hip_stream=stream.cuda_stream,
+                                   segment_rows=args.segment_rows)
     h = M.ifdlbm_create(cav, opt)
-    seg_rows = None
-    if args.autotune_steps > 0:
+    seg_rows = args.segment_rows or None
+    if args.autotune_steps > 0 and not args.segment_rows:
         seg_rows, tuned_ms = M.ifdlbm_autotune(h, args.autotune_steps)
         log("autotune: %d-row segments, %.3f ms/step in its trials" % (seg_rows, tuned_ms))
     info = M.ifdlbm_info(h)
