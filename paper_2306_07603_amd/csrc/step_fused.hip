@@ -55,6 +55,9 @@ constexpr int kRing = 5;                         // ring slots: rows t - 4 .. t
 #ifndef IFD_SRF_D64
 #define IFD_SRF_D64 1   // FP32SRF: the non-equilibrium part e - g of stage A in FP64 (0: in FP32)
 #endif
+#ifndef IFD_STORE_AUX
+#define IFD_STORE_AUX 0   // cache-policy bits of the state stores (2: non-temporal)
+#endif
 #ifndef IFD_FUSED_WAVES_F32
 #define IFD_FUSED_WAVES_F32 2
 #endif
@@ -88,7 +91,7 @@ template <> struct Buf<double> {
     __device__ static void st(double v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
     {
         using W = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0u, 0));
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(W, v), r, vo, so, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(W, v), r, vo, so, IFD_STORE_AUX);
     }
 };
 template <> struct Buf<float> {
@@ -98,7 +101,7 @@ template <> struct Buf<float> {
     }
     __device__ static void st(float v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
     {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, vo, so, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, vo, so, IFD_STORE_AUX);
     }
 };
 template <> struct Buf<__half> {
@@ -108,7 +111,7 @@ template <> struct Buf<__half> {
     }
     __device__ static void st(__half v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
     {
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, vo, so, 0);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, vo, so, IFD_STORE_AUX);
     }
 };
 
@@ -568,7 +571,7 @@ struct March {
         // ------------------------------------------------------------ C: row t - 4
         if (do_c) {
             T hp[9], gn[9];
-            T rem[9];   // exact final update (FP32SRF): value = gn + rem, rem the part below gn's rounding
+            double fin[S::kExactFinal ? 9 : 1];   // exact final update (FP32SRF): the FP64 sum of each population
             eta_ghosts<sf(R, 6), sf(R, 5), sf(R, 4), sf(R, 3), sf(R, 2)>(fh, p == 1, p == ny - 2);
             const MixedWeights<T> mx(eps, sx_c * geo[p]), my(eps, sy_c);
             if constexpr (S::kExactFinal) {
@@ -580,9 +583,8 @@ struct March {
                 transport<sf(R, 6), sf(R, 5), sf(R, 4), sf(R, 3), sf(R, 2)>(fh, hp, mx, my, p == 1, p == ny - 2, gn);
 #pragma unroll
                 for (int k = 0; k < 9; ++k) {
-                    const double v = (double)S::cvt(gcr[k], k) + (double)gn[k];
-                    gn[k] = T(v);
-                    rem[k] = T(v - (double)gn[k]);
+                    fin[k] = (double)S::cvt(gcr[k], k) + (double)gn[k];
+                    gn[k] = T(fin[k]);   // the FP32 value, for the wall extrapolation and the residual
                 }
             } else {
                 const int hs = hslot(p);
@@ -602,9 +604,9 @@ struct March {
             }
             if (out_col) {
                 if constexpr (S::kExactFinal) {
-                    double fin[9];
 #pragma unroll
-                    for (int k = 0; k < 9; ++k) fin[k] = wall_lane ? (double)gn[k] : (double)gn[k] + (double)rem[k];
+                    for (int k = 0; k < 9; ++k)
+                        if (wall_lane) fin[k] = (double)gn[k];
                     store_row(p, fin);
                 } else {
                     store_row(p, gn);
