@@ -61,10 +61,12 @@ def to_steady(h, tol: float, max_steps: int, chunk: int = 100000, label: str = "
 
 
 def regime(n_side: int = 257, time_units: float = 3000.0, every: int = 50, precision: str = "fp32srf",
-           chunk: int = 100000, steady_tol: float = 1e-4) -> dict:
-    """Run every case of PAPER_REGIMES for `time_units` (lid speed 0.1, height
-    1), record every `every` steps, classify the second half of the record."""
-    cav = [M.Cavity(n_side, n_side, re, n, th, 0.1) for th, n, re, _ in PAPER_REGIMES]
+           chunk: int = 100000, steady_tol: float = 1e-4, cases=None) -> dict:
+    """Run the cases of PAPER_REGIMES (all, or the listed indices) for
+    `time_units` (lid speed 0.1, height 1), record every `every` steps,
+    classify the second half of the record."""
+    table = [PAPER_REGIMES[i] for i in cases] if cases else PAPER_REGIMES
+    cav = [M.Cavity(n_side, n_side, re, n, th, 0.1) for th, n, re, _ in table]
     o = M.ifdlbm_default_options(precision=precision, residual_every=1000, graph_steps=1000)
     h = M.ifdlbm_create(cav, o)
     dts = [M.ifdlbm_time_step(h, c) for c in range(len(cav))]
@@ -82,7 +84,7 @@ def regime(n_side: int = 257, time_units: float = 3000.0, every: int = 50, preci
         log("regime: %d / %d steps, %.0f s" % (done, steps, time.time() - t0))
     ru, _ = M.ifdlbm_get_residuals(h)
     out = []
-    for c, (th, n, re, paper) in enumerate(PAPER_REGIMES):
+    for c, (th, n, re, paper) in enumerate(table):
         st, u, v, ke = M.ifdlbm_get_record(h, c, cap)
         half = st.size // 2
         dt_sample = every * dts[c]
@@ -294,10 +296,13 @@ def main(argv=None) -> int:
     ap.add_argument("--time-units", type=float, default=None, help="regime / stress: simulated time")
     ap.add_argument("--modes", default="", help="precision: comma-separated FP32 storage modes to compare")
     ap.add_argument("--max-steps", type=int, default=None, help="precision: step limit of the FP64 runs")
+    ap.add_argument("--cases", default="", help="regime: comma-separated indices into the paper's regime table")
     args = ap.parse_args(argv)
     kw = {}
     if args.time_units is not None and args.name in ("regime", "stress"):
         kw["time_units"] = args.time_units
+    if args.name == "regime" and args.cases:
+        kw["cases"] = [int(x) for x in args.cases.split(",")]
     if args.name == "precision":
         if args.modes:
             kw["modes"] = tuple(args.modes.split(","))
