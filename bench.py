@@ -179,6 +179,9 @@ def main() -> int:
     torch.cuda.set_stream(stream)
     specs = W.batch_sweep()
     cav = [M.Cavity(**s.__dict__) for s in specs]
+    pr = torch.cuda.get_device_properties(0)
+    device = {"name": pr.name, "arch": getattr(pr, "gcnArchName", ""), "compute_units": pr.multi_processor_count,
+              "memory_gib": round(pr.total_memory / 2**30, 1)}
 
     opt = M.ifdlbm_default_options(precision=args.precision, kernel=args.kernel, residual_every=args.residual_every,
                                    graph_steps=args.graph_steps, batched=1, hip_stream=stream.cuda_stream,
@@ -263,6 +266,7 @@ def main() -> int:
         "other_fp32_storage_modes": other or None,
         "speedup_vs_fp64_plain": (mlups / plain["value"]) if plain else None,
         "cpu_baseline": cpu,
+        "device": device,
     }
     print(json.dumps(out))
     return 0
