@@ -53,16 +53,16 @@ typedef struct ifdlbm_s ifdlbm_t;
 /* storage / compute precision (options.precision) */
 #define IFDLBM_FP64     0   /* FP64 distributions and relaxation time, FP64 arithmetic           */
 #define IFDLBM_FP32     1   /* FP32 deviations f-hat - omega_k rho0, FP32 arithmetic             */
-#define IFDLBM_FP16DEV  2   /* FP16 scaled deviations (f-hat - omega_k rho0)/omega_k, FP32 lambda
-                               and FP32 arithmetic                                                 */
+#define IFDLBM_FP16DEV  2   /* FP16 scaled deviations (f-hat - omega_k rho0)/omega_k stored with
+                               stochastic rounding, FP32 lambda and FP32 arithmetic                */
 #define IFDLBM_FP32X    3   /* FP32 deviations and lambda in memory, FP64 arithmetic               */
 #define IFDLBM_FP32SR   4   /* FP32 deviations stored with stochastic rounding (unbiased: no constant
                                forcing of a steady state by the rounding), FP64 arithmetic of the
                                distributions, FP32 arithmetic of Step (2)                          */
 #define IFDLBM_FP32SRF  5   /* FP32 deviations stored with stochastic rounding, FP32 arithmetic
-                               except the final update of each stored value: f-hat+ is rebuilt in
-                               FP64 from the stored f-hat and the FP32 streaming increment added
-                               in FP64 before the rounding                                         */
+                               except two FP64 steps: the non-equilibrium part e - g of Step (2)
+                               from the stored g, and the final value, the stored g plus the FP32
+                               collision and streaming increments, summed before the rounding      */
 
 /* kernel schedule (options.kernel) */
 #define IFDLBM_KERNEL_FUSED    0   /* one fused launch per step (default)                        */

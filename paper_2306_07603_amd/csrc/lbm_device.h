@@ -161,12 +161,14 @@ template <> struct Storage<P_FP32SR> {
     __device__ static inline void store(F* p, int64_t i, int k, T v) { p[i] = enc(v, k); }
 };
 
-// FP32 storage with stochastic rounding, FP32 arithmetic, except the final
-// update of each stored value: f-hat+ = g + b_hat (e - g) is rebuilt in FP64
-// from the stored (exact) g, the streaming increment of Eq. (3.6), computed in
-// FP32, is added in FP64, and the sum is rounded stochastically.  The rounding
-// errors left in FP32 are those of increments and of the half-step values that
-// only enter difference stencils, not of a stored state.
+// FP32 storage with stochastic rounding, FP32 arithmetic, except where the
+// exact stored g meets a small increment: e - g of Step (2) is formed in FP64,
+// and the new value g + (collision increment of Eq. 2.15 + streaming increment
+// of Eq. 3.6) is summed in FP64 from the stored g and rounded stochastically
+// (the increments are FP32, each accurate relative to itself; the staged
+// schedule rebuilds f-hat+ in FP64 instead).  The rounding errors left in FP32
+// are those of increments and of the half-step values that only enter
+// difference stencils, not of a stored state.
 template <> struct Storage<P_FP32SRF> {
     static constexpr bool kStochastic = true;
     static constexpr bool kExactFinal = true;
