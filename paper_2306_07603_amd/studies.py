@@ -61,13 +61,13 @@ def to_steady(h, tol: float, max_steps: int, chunk: int = 100000, label: str = "
 
 
 def regime(n_side: int = 257, time_units: float = 3000.0, every: int = 50, precision: str = "fp32srf",
-           chunk: int = 100000, steady_tol: float = 1e-4, cases=None) -> dict:
+           chunk: int = 100000, steady_tol: float = 1e-4, cases=None, mix: float = 0.5) -> dict:
     """Run the cases of PAPER_REGIMES (all, or the listed indices) for
     `time_units` (lid speed 0.1, height 1), record every `every` steps,
     classify the second half of the record."""
     table = [PAPER_REGIMES[i] for i in cases] if cases else PAPER_REGIMES
     cav = [M.Cavity(n_side, n_side, re, n, th, 0.1) for th, n, re, _ in table]
-    o = M.ifdlbm_default_options(precision=precision, residual_every=1000, graph_steps=1000)
+    o = M.ifdlbm_default_options(precision=precision, residual_every=1000, graph_steps=1000, mix=mix)
     h = M.ifdlbm_create(cav, o)
     dts = [M.ifdlbm_time_step(h, c) for c in range(len(cav))]
     steps = int(time_units / min(dts))
@@ -99,6 +99,7 @@ def regime(n_side: int = 257, time_units: float = 3000.0, every: int = 50, preci
                rk["harmonic_fraction"] if rk else 0, rc_["name"] if rc_ else "non-finite",
                rc_["f_main"] if rc_ else 0, ru[c]))
     return {"study": "regime", "n_side": n_side, "time_units": time_units, "every": every, "precision": precision,
+            "mix": mix,
             "steady_tol": steady_tol, "steps": steps, "seconds": time.time() - t0, "cases": out}
 
 
@@ -297,12 +298,15 @@ def main(argv=None) -> int:
     ap.add_argument("--modes", default="", help="precision: comma-separated FP32 storage modes to compare")
     ap.add_argument("--max-steps", type=int, default=None, help="precision: step limit of the FP64 runs")
     ap.add_argument("--cases", default="", help="regime: comma-separated indices into the paper's regime table")
+    ap.add_argument("--mix", type=float, default=None, help="regime: central weight of Eq. (2.5)")
     args = ap.parse_args(argv)
     kw = {}
     if args.time_units is not None and args.name in ("regime", "stress"):
         kw["time_units"] = args.time_units
     if args.name == "regime" and args.cases:
         kw["cases"] = [int(x) for x in args.cases.split(",")]
+    if args.name == "regime" and args.mix is not None:
+        kw["mix"] = args.mix
     if args.name == "precision":
         if args.modes:
             kw["modes"] = tuple(args.modes.split(","))
