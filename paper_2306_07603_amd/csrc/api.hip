@@ -56,7 +56,7 @@ constexpr double kCs2 = 1.0 / 3.0;
 // are at most kStripOut).  Automatic choice: the longest segment (fewest
 // recomputed halo rows) that still gives kTargetItems work items, so that the
 // GPU stays full through the tail of a launch; the shortest otherwise.
-constexpr int kSegCandidates[] = {128, 96, 64, 48, 32, 24, 16};
+constexpr int kSegCandidates[] = {128, 96, 80, 72, 64, 56, 48, 40, 32, 24, 16};
 constexpr int kMinSegRows = 8;
 constexpr int kTargetItems = 4096;
 constexpr int kXcds = 8;   // MI355X: workgroups are dealt to the 8 XCDs in turn
