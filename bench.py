@@ -163,7 +163,7 @@ def main() -> int:
     if args.copy_calibration:
         return copy_calibration()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (cavities are independent; "
+        print("bench.py measures one GPU: the library has no multi-GPU path (cavities are independent; "
               "the batch would shard across GPUs with no communication).", file=sys.stderr)
         return 2
 
