@@ -143,7 +143,7 @@ def copy_calibration() -> int:
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--kernel", default="fused", choices=["fused", "staged"])
     ap.add_argument("--precision", default="fp32srf", choices=["fp32srf", "fp32sr", "fp32", "fp32x", "fp16dev", "fp64"])
