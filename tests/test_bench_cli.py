@@ -1,0 +1,24 @@
+"""bench.py's command line on the CPU: more than one GPU is refused with a
+message, and the kernel-source digest that gates the counter record is
+stable and covers the step kernel's sources."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_kernel_source_digest():
+    sys.path.insert(0, ROOT)
+    import bench
+    d = bench.kernel_source_digest()
+    assert len(d) == 64 and d == bench.kernel_source_digest()
+    assert any(p.endswith("step_fused.hip") for p in bench.KERNEL_SOURCES)
+    assert bench.measured_record("no-such-precision", "bytes") is None
