@@ -99,7 +99,7 @@ typedef struct {
 typedef struct {
     int32_t precision;      /* IFDLBM_FP64 | _FP32 | _FP16DEV | _FP32X | _FP32SR | _FP32SRF            */
     double  cfl;            /* Courant number, > 0 (paper: 0.5); dt follows dt_rule                   */
-    double  mix;            /* weight of the central scheme in Eq. (2.5), [0, 1] (default 0.5)       */
+    double  mix;            /* weight of the central scheme in Eq. (2.5), [0, 1] (default 0.75)      */
     double  rho0;           /* constant density of Eq. (2.8) (default 1); u and P do not depend on it */
     double  gamma_min;      /* floor of the shear rate in Eq. (1.4), > 0 (default 1e-6)              */
     int32_t residual_every; /* evaluate Eq. (2.19) every this many steps, >= 1 (paper: 1)             */
@@ -123,7 +123,7 @@ typedef struct {
     int64_t work_items;         /* workgroups of the step kernel                                       */
 } ifdlbm_info_t;
 
-/* Fills *opt with the defaults: FP64, cfl 0.5, mix 0.5, rho0 1, gamma_min 1e-6, residual_every 1,
+/* Fills *opt with the defaults: FP64, cfl 0.5, mix 0.75, rho0 1, gamma_min 1e-6, residual_every 1,
    fused kernel, batched, no graph, contravariant time-step rule, automatic segment rows, lagged lambda,
    null stream. */
 int ifdlbm_default_options(ifdlbm_options* opt);

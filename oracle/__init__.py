@@ -128,7 +128,7 @@ class Params:
     theta_deg: float = 90.0
     u_lid: float = 0.1
     cfl: float = 0.5
-    mix: float = 0.5
+    mix: float = 0.75
     rho0: float = 1.0
     gamma_min: float = 1e-6
     bc_mode: int = CAVITY

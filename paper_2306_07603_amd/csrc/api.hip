@@ -472,7 +472,7 @@ int ifdlbm_default_options(ifdlbm_options* opt)
     std::memset(opt, 0, sizeof(*opt));
     opt->precision = IFDLBM_FP64;
     opt->cfl = 0.5;
-    opt->mix = 0.5;
+    opt->mix = 0.75;
     opt->rho0 = 1.0;
     opt->gamma_min = 1e-6;
     opt->residual_every = 1;

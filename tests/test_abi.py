@@ -32,7 +32,7 @@ def test_binding_has_same_names():
 
 def test_default_options():
     o = M.ifdlbm_default_options()
-    assert o.precision == M.IFDLBM_FP64 and o.cfl == 0.5 and o.mix == 0.5 and o.rho0 == 1.0
+    assert o.precision == M.IFDLBM_FP64 and o.cfl == 0.5 and o.mix == 0.75 and o.rho0 == 1.0
     assert o.gamma_min == 1e-6 and o.residual_every == 1 and o.batched == 1 and o.graph_steps == 0
     assert o.segment_rows == 0 and o.dt_rule == M.IFDLBM_DT_CONTRAVARIANT
 
