@@ -29,7 +29,7 @@ METRIC = "MLUPS & % HBM roofline, FP32-batched vs plain FP64 on GPU at ≤1e-5 v
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, published
 VALU_PEAK_GINST = 256 * 4 * 2.4 / 4   # wave64 VALU instructions per ns: 256 CUs, 4 SIMD16 each, 2.4 GHz
 WORKLOAD = ("256-cavity uneven batch: sides {65,129,257,513}, Re log-uniform [100,5000], n uniform [0.5,1.5], "
-            "theta uniform [40,90] deg, lid 0.1, CFL 0.5; FP64 residual sums every 100 steps, "
+            "theta uniform [40,90] deg, lid 0.1, CFL 0.5, central weight 0.75; FP64 residual sums every 100 steps, "
             "one launch per step, HIP-graph replay")
 # storage of the distributions and arithmetic type of each precision mode
 PRECISION = {

@@ -61,13 +61,15 @@ def to_steady(h, tol: float, max_steps: int, chunk: int = 100000, label: str = "
 
 
 def regime(n_side: int = 257, time_units: float = 3000.0, every: int = 50, precision: str = "fp32srf",
-           chunk: int = 100000, steady_tol: float = 1e-4, cases=None, mix: float = 0.5) -> dict:
+           chunk: int = 100000, steady_tol: float = 1e-4, cases=None, mix=None) -> dict:
     """Run the cases of PAPER_REGIMES (all, or the listed indices) for
     `time_units` (lid speed 0.1, height 1), record every `every` steps,
     classify the second half of the record."""
     table = [PAPER_REGIMES[i] for i in cases] if cases else PAPER_REGIMES
     cav = [M.Cavity(n_side, n_side, re, n, th, 0.1) for th, n, re, _ in table]
-    o = M.ifdlbm_default_options(precision=precision, residual_every=1000, graph_steps=1000, mix=mix)
+    o = M.ifdlbm_default_options(precision=precision, residual_every=1000, graph_steps=1000)
+    if mix is not None:
+        o.mix = mix
     h = M.ifdlbm_create(cav, o)
     dts = [M.ifdlbm_time_step(h, c) for c in range(len(cav))]
     steps = int(time_units / min(dts))
@@ -99,7 +101,7 @@ def regime(n_side: int = 257, time_units: float = 3000.0, every: int = 50, preci
                rk["harmonic_fraction"] if rk else 0, rc_["name"] if rc_ else "non-finite",
                rc_["f_main"] if rc_ else 0, ru[c]))
     return {"study": "regime", "n_side": n_side, "time_units": time_units, "every": every, "precision": precision,
-            "mix": mix,
+            "mix": o.mix,
             "steady_tol": steady_tol, "steps": steps, "seconds": time.time() - t0, "cases": out}
 
 
@@ -176,8 +178,8 @@ def lag(n_side: int = 65) -> dict:
     return out
 
 
-STRESS_VARIANTS = [("default (mix 0.5, CFL 0.5)", {}), ("central stencil (mix 1)", {"mix": 1.0}),
-                   ("mix 0.75", {"mix": 0.75}), ("CFL 0.25", {"cfl": 0.25})]
+STRESS_VARIANTS = [("mix 0.5, CFL 0.5", {"mix": 0.5}), ("central stencil (mix 1)", {"mix": 1.0}),
+                   ("mix 0.75 (default)", {"mix": 0.75}), ("CFL 0.25, mix 0.5", {"cfl": 0.25, "mix": 0.5})]
 
 
 def stress(n_side: int = 129, time_units: float = 500.0) -> dict:
