@@ -204,15 +204,31 @@ __device__ __forceinline__ T lds_at(const T* row, uint32_t byte_offset)
     return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(row) + byte_offset);
 }
 
-// LDS of one wavefront.
-template <typename T>
+// LDS of one wavefront.  NG is 9 where stage C reads the stored row again
+// (exact final update), else 0.
+template <typename T, int NG>
 struct WaveLds {
     T xs[8][kRowLds];                 // one row of each moving population, for the xi stencils
     T hp[kRing][9][kWaveLanes];       // f-hat+ of rows t-4 .. t (lane-private); the slot of row ny keeps
                                       // f-bar of row ny-2 for the lid row of the half step
     T wb[2][9];                       // f-bar of columns 1 and nx-2 at the current half-step row
     T wc[2][9];                       // f-hat(t+dt) of columns 1 and nx-2 at the current full-step row
+    T gx[NG][kWaveLanes];             // stored f-hat of the stage-C row, written by the buffer unit
 };
+
+// Compiler-level memory barrier: no memory operation is moved across it, and
+// it emits no instruction.
+__device__ __forceinline__ void mem_order() { asm volatile("" ::: "memory"); }
+
+// Waits until at most N vector-memory operations of this wave are outstanding.
+// The counter completes in issue order, so an operation followed by at least
+// N others has then finished.
+template <int N>
+__device__ __forceinline__ void wait_vm()
+{
+    static_assert(N >= 0 && N <= 63, "vmcnt range");
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
 
 template <typename T>
 __device__ __forceinline__ void publish(T (*w)[9], int i, int nx, const T (&x)[9])
@@ -280,7 +296,7 @@ struct March {
     const StepArgs& a;
     const StripItem& it;
     const CavityDesc& c;
-    WaveLds<T>& sh;
+    WaveLds<T, S::kExactFinal ? 9 : 0>& sh;
     double (&acc)[kPartials];
 
     int lane, nx, ny, i, ic, j0, j1, qlo, qhi, t_begin, t_last;
@@ -289,7 +305,10 @@ struct March {
     V dtv;
     T ulid, sx_b, sy_b, sx_c, sy_c;
     T eps;
-    const T* geo;
+    // the row metric a_j, read-only while a step runs: through the constant address space a row's value
+    // (uniform over the wave) comes by a scalar load, on the scalar counter, so that waiting for it does not
+    // also wait for the vector loads of the next row in flight
+    const __attribute__((address_space(4))) T* geo;
     XiLane<T, EDGE> xl;
     __amdgpu_buffer_rsrc_t rf_in, rf_out, rl_in, rl_out;
     uint32_t fpb;          // bytes per distribution plane
@@ -302,7 +321,8 @@ struct March {
     F gn_[9];              // f-hat of row t + 1, in flight
     L ln_;
 
-    __device__ __forceinline__ March(const StepArgs& a_, const StripItem& it_, const CavityDesc& c_, WaveLds<T>& sh_,
+    __device__ __forceinline__ March(const StepArgs& a_, const StripItem& it_, const CavityDesc& c_,
+                                     WaveLds<T, S::kExactFinal ? 9 : 0>& sh_,
                                      double (&acc_)[kPartials])
         : a(a_), it(it_), c(c_), sh(sh_), acc(acc_), pl(c_),
           xl(threadIdx.x, it_.i0 - kHaloCols + (int)threadIdx.x, c_.nx,
@@ -330,7 +350,7 @@ struct March {
         sx_b = T(0.5) * dt * T(c.inv2dxi);
         sx_c = dt * T(c.inv2dxi);
         eps = T(c.mix);
-        geo = geo_of<T>(a) + c.geo_off;
+        geo = (const __attribute__((address_space(4))) T*)(geo_of<T>(a) + c.geo_off);
         fpb = (uint32_t)c.plane * (uint32_t)sizeof(F);
         rf_in = buffer_of(static_cast<const F*>(a.f_in) + c.f_off, 9u * fpb);
         rf_out = buffer_of(static_cast<F*>(a.f_out) + c.f_off, 9u * fpb);
@@ -365,6 +385,20 @@ struct March {
 #pragma unroll
         for (int k = 0; k < 9; ++k) gn_[k] = Buf<F>::ld(rf_in, vo, (uint32_t)k * fpb);
         ln_ = Buf<L>::ld(rl_in, loff(row), 0u);
+    }
+
+    // Exact final update: the stored f-hat of `row` copied by the buffer unit
+    // straight into sh.gx, so that no registers are held while it is in flight.
+    // The compiler does not track these copies: the reader waits on the
+    // vector-memory counter itself (wait_vm).
+    __device__ __forceinline__ void reload_lds(int row)
+    {
+        static_assert(sizeof(F) == 4, "the LDS copy moves one dword per lane");
+        const uint32_t vo = foff(row);
+#pragma unroll
+        for (int k = 0; k < 9; ++k)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rf_in, (__attribute__((address_space(3))) void*)&sh.gx[k][0], 4u,
+                                                    vo, (uint32_t)k * fpb, 0, 0);
     }
 
     // old moments of row `row` (residual only)
@@ -470,7 +504,9 @@ struct March {
     {
         const int p = t - 4;
         const bool do_c = p >= j0 && p < j1 && p >= 1 && p <= ny - 2;
-        F gcr[9];   // exact final update: the stored f-hat of row p, read again before stage B
+        // exact final update: the stored f-hat of row p goes to LDS first, ahead of the fetch of row t + 1,
+        // so that stage C's wait for it leaves that fetch in flight
+        const bool fetch_next = t <= ny - 1 && t + 1 <= t_last;
 
         // ------------------------------------------------------------ A: row t
         if (t <= ny - 1) {
@@ -479,7 +515,17 @@ struct March {
 #pragma unroll
             for (int k = 0; k < 9; ++k) g[k] = S::cvt(gn_[k], k);
             const V lam_old = V(ln_);
-            if (t + 1 <= t_last) fetch(t + 1);   // consumed by the next row
+            if constexpr (S::kExactFinal) {
+                // the fetched row is waited for here, before the LDS copy is issued, so that the wait does not
+                // cover the copy as well
+#pragma unroll
+                for (int k = 0; k < 9; ++k) asm volatile("" ::"v"(g[k]));
+                asm volatile("" ::"v"(lam_old));
+                mem_order();
+                if (do_c) reload_lds(p);
+                mem_order();
+            }
+            if (fetch_next) fetch(t + 1);   // consumed by the next row (ten vector-memory loads)
             V l;
             if constexpr (S::kExactFinal && IFD_SRF_D64) {
                 // e - g in FP64 from the exact stored g: at low shear the non-equilibrium part is far below
@@ -512,14 +558,10 @@ struct March {
             }
             lam[sg(R, 0)] = l;
             if (out_col && t >= j0 && t < j1) Buf<L>::st(L(l), rl_out, loff(t), 0u);
-        }
-
-        if constexpr (S::kExactFinal) {
-            if (do_c) {
-                const uint32_t vo = foff(p);
-#pragma unroll
-                for (int k = 0; k < 9; ++k) gcr[k] = Buf<F>::ld(rf_in, vo, (uint32_t)k * fpb);
-            }
+        } else if constexpr (S::kExactFinal) {
+            mem_order();
+            if (do_c) reload_lds(p);
+            mem_order();
         }
 
         // ------------------------------------------------------------ B: row t - 2
@@ -581,9 +623,13 @@ struct March {
 #pragma unroll
                 for (int k = 0; k < 9; ++k) hp[k] = sh.hp[hs][k][lane];
                 transport<sf(R, 6), sf(R, 5), sf(R, 4), sf(R, 3), sf(R, 2)>(fh, hp, mx, my, p == 1, p == ny - 2, gn);
+                if (fetch_next)
+                    wait_vm<10>();   // the LDS copy of row p was followed by the ten loads of row t + 1
+                else
+                    wait_vm<0>();
 #pragma unroll
                 for (int k = 0; k < 9; ++k) {
-                    fin[k] = (double)S::cvt(gcr[k], k) + (double)gn[k];
+                    fin[k] = (double)S::cvt(sh.gx[k][lane], k) + (double)gn[k];
                     gn[k] = T(fin[k]);   // the FP32 value, for the wall extrapolation and the residual
                 }
             } else {
@@ -706,7 +752,7 @@ __global__ __launch_bounds__(kWaveLanes, Tuning<PREC>::kWaves) void k_fused(Step
     const StripItem it = items[w];
     if (it.unit < 0) return;   // padding of a per-XCD queue
     const CavityDesc c = a.desc[it.cav];
-    __shared__ WaveLds<typename Storage<PREC>::T> sh;
+    __shared__ WaveLds<typename Storage<PREC>::T, Storage<PREC>::kExactFinal ? 9 : 0> sh;
     double acc[kPartials] = {0, 0, 0, 0, 0, 0, 0};
     // waves that hold column 1 or nx-2 take the first-order one-sided points (Eq. 2.7 at walls)
     if (IFD_FUSED_ONE_PATH || it.i0 <= 5 || it.i1 >= c.nx - 5)
