@@ -76,6 +76,10 @@ struct Tuning {
 // Dword 3 of a raw buffer resource on the gfx9 family (CDNA): 32-bit data
 // format, no swizzle, no index stride.
 constexpr int kRawBufferWord3 = 0x00020000;
+// A buffer offset beyond any buffer of the step (the state of one cavity is far
+// below 2 GiB): loads from it return 0 and stores to it are dropped by the
+// range check of raw buffers.
+constexpr uint32_t kDroppedOffset = 0x80000000u;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* p, uint32_t bytes)
 {
@@ -420,6 +424,25 @@ struct March {
         for (int k = 0; k < 9; ++k) Buf<F>::st(encode_state<S>(x[k], k, &nw), rf_out, vo, (uint32_t)k * fpb);
     }
 
+    template <typename X>
+    __device__ __forceinline__ void encode_row(int row, const X (&x)[9], F (&e)[9]) const
+    {
+        const NodeWords nw(skey, ckey, (uint32_t)(row * pitch + i));
+#pragma unroll
+        for (int k = 0; k < 9; ++k) e[k] = encode_state<S>(x[k], k, &nw);
+    }
+
+    // A store that every path of the row issues: lanes (or rows) with `on` false
+    // take an offset past the end of the buffer, and the buffer unit drops such
+    // stores.  The compiler's wait for the row fetched ahead then counts these
+    // stores as issued after it instead of draining them.
+    __device__ __forceinline__ void store_encoded(int row, const F (&e)[9], bool on) const
+    {
+        const uint32_t vo = on ? foff(row) : kDroppedOffset;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Buf<F>::st(e[k], rf_out, vo, (uint32_t)k * fpb);
+    }
+
     // out[k] = base[k] - sx * a_j d_k * D_xi - sy * D_eta for the moving
     // populations of one row, where D are the signed mixed differences: xi
     // neighbours from the LDS row, eta neighbours from ring slots s[0..4]
@@ -557,7 +580,7 @@ struct March {
                 sh.hp[hs][k][lane] = S::kExactFinal ? b_hat * d[k] : g[k] + b_hat * d[k];
             }
             lam[sg(R, 0)] = l;
-            if (out_col && t >= j0 && t < j1) Buf<L>::st(L(l), rl_out, loff(t), 0u);
+            Buf<L>::st(L(l), rl_out, out_col && t >= j0 && t < j1 ? loff(t) : kDroppedOffset, 0u);
         } else if constexpr (S::kExactFinal) {
             mem_order();
             if (do_c) reload_lds(p);
@@ -611,6 +634,7 @@ struct March {
         }
 
         // ------------------------------------------------------------ C: row t - 4
+        F enc[9];   // the encoded row p, stored after the branch
         if (do_c) {
             T hp[9], gn[9];
             double fin[S::kExactFinal ? 9 : 1];   // exact final update (FP32SRF): the FP64 sum of each population
@@ -648,20 +672,18 @@ struct March {
                     extrapolate(src, T(0), gn);
                 }
             }
-            if (out_col) {
-                if constexpr (S::kExactFinal) {
+            if constexpr (S::kExactFinal) {
 #pragma unroll
-                    for (int k = 0; k < 9; ++k)
-                        if (wall_lane) fin[k] = (double)gn[k];
-                    store_row(p, fin);
-                } else {
-                    store_row(p, gn);
-                }
-                if (RES) {
-                    T old[3];
-                    old_moments(p, old);
-                    residual_add(gn, old, acc);
-                }
+                for (int k = 0; k < 9; ++k)
+                    if (wall_lane) fin[k] = (double)gn[k];
+                encode_row(p, fin, enc);
+            } else {
+                encode_row(p, gn, enc);
+            }
+            if (RES && out_col) {
+                T old[3];
+                old_moments(p, old);
+                residual_add(gn, old, acc);
             }
             if (p == 1 && j0 == 0) {   // bottom wall row from row 1
                 T src[9], g0[9];
@@ -690,6 +712,7 @@ struct March {
                 }
             }
         }
+        store_encoded(p, enc, do_c && out_col);
     }
 
     __device__ __forceinline__ void rotate()
