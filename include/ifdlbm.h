@@ -131,9 +131,10 @@ int ifdlbm_default_options(ifdlbm_options* opt);
 /* Validates cav[0..n_cav) and *opt, builds the metric terms of Eqs. (3.2)-(3.8.2) in FP64 on the host,
    allocates the device state and applies Step (1): u = 0, P = 0 except u = (u_lid, 0) on the top row
    (corners included), f-hat = f_eq, lambda = U / (Re c_s^2).  *out receives the handle.
-   Size limits: n_xi <= 32767 and n_eta * pitch <= 2^25 nodes per cavity (pitch = n_xi rounded up to a
-   multiple of 16), so that the nine planes of one cavity span less than 4 GiB in FP64 and are addressed with
-   32-bit byte offsets.
+   Size limits: n_xi <= 32767 and n_eta * pitch <= 2^24 nodes per cavity (pitch = n_xi rounded up to a
+   multiple of 16), so that the nine planes of one cavity span less than 2 GiB in FP64 and are addressed with
+   32-bit byte offsets (offsets of 2 GiB and above are past every buffer: the step kernels store there what
+   they drop).
    Errors: EINVAL (bad argument, nothing allocated), ENOMEM, EDEVICE. */
 int ifdlbm_create(const ifdlbm_cavity* cav, int32_t n_cav, const ifdlbm_options* opt, ifdlbm_t** out);
 

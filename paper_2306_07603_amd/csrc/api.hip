@@ -508,9 +508,10 @@ static int ifdlbm_create_impl(const ifdlbm_cavity* cav, int32_t n_cav, const ifd
         const ifdlbm_cavity& v = cav[c];
         const std::string id = "cavity " + std::to_string(c) + ": ";
         if (v.n_xi < 5 || v.n_eta < 5) return fail(IFDLBM_EINVAL, id + "n_xi and n_eta must be >= 5");
-        // 32-bit byte offsets over the nine planes of a cavity: 9 * n_eta * pitch * 8 < 2^32
-        if (v.n_xi > 32767 || (int64_t)((v.n_xi + 15) / 16 * 16) * v.n_eta > (int64_t)1 << 25)
-            return fail(IFDLBM_EINVAL, id + "grid too large (n_xi <= 32767, n_eta * pitch <= 2^25)");
+        // the nine FP64 planes of a cavity span at most 9 * 2^24 * 8 bytes (1.125 GiB): every byte offset of the
+        // step kernels, and the 2^31 offset their dropped stores use, stay below 2^32
+        if (v.n_xi > 32767 || (int64_t)((v.n_xi + 15) / 16 * 16) * v.n_eta > (int64_t)1 << 24)
+            return fail(IFDLBM_EINVAL, id + "grid too large (n_xi <= 32767, n_eta * pitch <= 2^24)");
         if (!(v.theta_deg > 0.0 && v.theta_deg <= 90.0)) return fail(IFDLBM_EINVAL, id + "theta_deg must be in (0, 90]");
         if (!(v.n > 0.0) || !std::isfinite(v.n)) return fail(IFDLBM_EINVAL, id + "n must be > 0");
         if (!(v.re > 0.0) || !std::isfinite(v.re)) return fail(IFDLBM_EINVAL, id + "re must be > 0");

@@ -76,9 +76,10 @@ struct Tuning {
 // Dword 3 of a raw buffer resource on the gfx9 family (CDNA): 32-bit data
 // format, no swizzle, no index stride.
 constexpr int kRawBufferWord3 = 0x00020000;
-// A buffer offset beyond any buffer of the step (the state of one cavity is far
-// below 2 GiB): loads from it return 0 and stores to it are dropped by the
-// range check of raw buffers.
+// A buffer offset beyond any buffer of the step (ifdlbm_create keeps the state
+// of one cavity below 1.2 GiB, and offset plus plane offset below 2^32): loads
+// from it return 0 and stores to it are dropped by the range check of raw
+// buffers.
 constexpr uint32_t kDroppedOffset = 0x80000000u;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* p, uint32_t bytes)

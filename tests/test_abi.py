@@ -51,6 +51,7 @@ BAD_CAVITIES = [
     M.Cavity(17, 17, 100.0, 1.0, 60.0, 0.0),   # lid at rest: Re of Eq. (2.15.1) undefined
     M.Cavity(17, 17, float("nan"), 1.0, 60.0),
     M.Cavity(5793, 5793, 100.0, 1.0, 60.0),   # nine FP64 planes would span 4 GiB or more
+    M.Cavity(4097, 4097, 100.0, 1.0, 60.0),   # n_eta * pitch above 2^24: FP64 planes past the 2 GiB drop offset
     M.Cavity(32768, 5, 100.0, 1.0, 60.0),     # n_xi beyond 16-bit column indices
 ]
 
