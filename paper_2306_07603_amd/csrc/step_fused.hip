@@ -671,16 +671,17 @@ struct March {
                     T src[9];
                     wall_source(sh.wc, i, nx, gn, src);
                     extrapolate(src, T(0), gn);
+                    if constexpr (S::kExactFinal) {
+#pragma unroll
+                        for (int k = 0; k < 9; ++k) fin[k] = (double)gn[k];   // the wall value replaces the sum
+                    }
                 }
             }
-            if constexpr (S::kExactFinal) {
-#pragma unroll
-                for (int k = 0; k < 9; ++k)
-                    if (wall_lane) fin[k] = (double)gn[k];
+            // (a lane at column 0 or nx - 1 of a wave without walls_c is a halo lane: nothing of it is stored)
+            if constexpr (S::kExactFinal)
                 encode_row(p, fin, enc);
-            } else {
+            else
                 encode_row(p, gn, enc);
-            }
             if (RES && out_col) {
                 T old[3];
                 old_moments(p, old);
