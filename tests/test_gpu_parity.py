@@ -126,6 +126,33 @@ def test_full_size_grids_fp64(kernel):
         h.close()
 
 
+@pytest.mark.parametrize("spec", [W.CavitySpec(4096, 4096, 1000.0, 1.0, 60.0),     # largest square: n_eta * pitch = 2^24
+                                  W.CavitySpec(32767, 512, 400.0, 0.8, 90.0)])     # widest: 32767 columns, pitch 32768
+def test_maximum_size_cavity_fp64(spec):
+    """A cavity at the size limit of ifdlbm_create (nine FP64 planes of 1.125 GiB in all), one step with each
+    kernel, whole fields against the oracle.  Stores that the step drops go past the end of these planes.
+    u, v, lambda, f-hat within 1e-12; P within the cancellation bound of recovering a small pressure from the
+    sums of the populations (3e-11, as at rho0 = 1)."""
+    steps = 1
+    uo, vo, po, Fo, Lo = O.simulate(oparams(spec), steps)
+    # one step after the start, v exists only next to the lid corners and is orders of magnitude below u: both
+    # components are measured against the velocity scale, so that an ulp of the lid speed does not count as a
+    # relative error of v
+    vs = max(np.abs(uo).max(), np.abs(vo).max())
+    print("max |u|", np.abs(uo).max(), "max |v|", np.abs(vo).max(), "max |P|", np.abs(po).max(), flush=True)
+    for kernel in KERNELS:
+        print("maximum size", spec, kernel, flush=True)
+        h = gpu([spec], steps, kernel=kernel)
+        u, v, p = M.ifdlbm_get_fields(h, 0)
+        F, L = M.ifdlbm_get_state(h, 0)
+        h.close()
+        errs = {"u": float(np.abs(u - uo).max() / vs), "v": float(np.abs(v - vo).max() / vs), "P": rel(p, po),
+                "lambda": rel(L, Lo), "fhat": rel(F, Fo)}
+        print(kernel, errs, flush=True)
+        for k, e in errs.items():
+            assert e <= (3e-11 if k == "P" else FP64_TOL), (kernel, k, e)
+
+
 @pytest.mark.parametrize("kernel", KERNELS)
 def test_batched_equals_unbatched_bitwise(kernel):
     specs = [W.CavitySpec(17, 17, 100.0, 0.8, 60.0), W.CavitySpec(65, 65, 1000.0, 1.2, 45.0),
