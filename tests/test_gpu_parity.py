@@ -151,6 +151,13 @@ def test_maximum_size_cavity_fp64(spec):
         print(kernel, errs, flush=True)
         for k, e in errs.items():
             assert e <= (3e-11 if k == "P" else FP64_TOL), (kernel, k, e)
+    # the benchmarked storage mode on the same planes (FP32: 0.56 GiB), fused kernel
+    h = gpu([spec], steps, "fp32srf", "fused")
+    u, v, _ = M.ifdlbm_get_fields(h, 0)
+    h.close()
+    errs = (float(np.abs(u - uo).max() / vs), float(np.abs(v - vo).max() / vs))
+    print("fp32srf fused errors u v", errs, flush=True)
+    assert errs[0] <= FP32_TOL and errs[1] <= FP32_TOL
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
