@@ -62,12 +62,13 @@ def kernel_source_digest() -> str:
     return h.hexdigest()
 
 
-def measured_record(precision: str, what: str):
-    """A per-launch figure of the step kernel recorded in profiles/ from rocprofv3
-    counter passes: what = "bytes" (FETCH_SIZE and WRITE_SIZE, each scaled by the
-    same counter's reading for a plain copy of known size) or "valu_insts"
-    (SQ_INSTS_VALU, wavefront instructions).  None when the record is absent or
-    was taken on other kernel sources."""
+def measured_record(precision: str, what: str, segment_rows):
+    """A per-launch figure of the step kernel at `segment_rows`-row segments,
+    recorded in profiles/ from rocprofv3 counter passes: what = "bytes"
+    (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter's reading for a
+    plain copy of known size) or "valu_insts" (SQ_INSTS_VALU, wavefront
+    instructions).  None when the record is absent, was taken on other kernel
+    sources or holds no figure for that segment length."""
     if not os.path.exists(TRAFFIC_RECORD):
         return None
     rec = {}
@@ -78,7 +79,9 @@ def measured_record(precision: str, what: str):
                 rec[k.strip()] = v.strip()
     if rec.get("kernel_sources_sha256") != kernel_source_digest():
         return None
-    key = "%s_per_launch_%s" % (what, precision)
+    if not segment_rows:
+        return None
+    key = "%s_per_launch_%s_seg%d" % (what, precision, segment_rows)
     return float(rec[key]) if key in rec else None
 
 
@@ -211,7 +214,7 @@ def main() -> int:
     log(args.precision + " batched: %.1f MLUPS, %.3f ms/step, kernel %.3f ms, %.0f GB/s" % (mlups, wall * 1e3 / args.steps, kernel_ms, achieved))
     # the vector-ALU issue rate of the same launches: SQ_INSTS_VALU per launch (counter record) over the
     # measured launch time, against 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per wave64 instruction
-    insts = measured_record(args.precision, "valu_insts")
+    insts = measured_record(args.precision, "valu_insts", seg_rows)
     valu = None
     if insts:
         rate = insts / (kernel_ms * 1e-3) / 1e9
@@ -259,7 +262,7 @@ def main() -> int:
                    "residual_every": args.residual_every, "graph_steps": args.graph_steps,
                    "segment_rows": seg_rows, "autotune_steps": args.autotune_steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_record(args.precision, "bytes"),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_record(args.precision, "bytes", seg_rows),
                      "kernel_ms": kernel_ms, "alg_bytes_per_launch": alg_bytes,
                      "alg_bytes_per_node": info["alg_bytes_per_node"], "valu": valu},
         "fp64_plain": plain,

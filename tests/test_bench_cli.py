@@ -21,4 +21,5 @@ def test_kernel_source_digest():
     d = bench.kernel_source_digest()
     assert len(d) == 64 and d == bench.kernel_source_digest()
     assert any(p.endswith("step_fused.hip") for p in bench.KERNEL_SOURCES)
-    assert bench.measured_record("no-such-precision", "bytes") is None
+    assert bench.measured_record("no-such-precision", "bytes", 48) is None
+    assert bench.measured_record("fp32srf", "bytes", None) is None
