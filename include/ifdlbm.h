@@ -107,7 +107,7 @@ typedef struct {
     int32_t batched;        /* 1: all cavities in one launch per step; 0: one launch per cavity       */
     int32_t graph_steps;    /* > 0: replay steps from a captured HIP graph of this many steps         */
     int32_t dt_rule;        /* IFDLBM_DT_CONTRAVARIANT | IFDLBM_DT_CARTESIAN                          */
-    int32_t segment_rows;   /* fused kernel: rows per work item, 0 = automatic, else in [16, 4096]    */
+    int32_t segment_rows;   /* fused kernel: rows per work item, 0 = automatic, else in [8, 4096]     */
     int32_t lambda_mode;    /* IFDLBM_LAMBDA_LAGGED (the paper's, default) | IFDLBM_LAMBDA_IMPLICIT    */
     void*   hip_stream;     /* hipStream_t to enqueue on, or NULL for the null stream                 */
 } ifdlbm_options;

@@ -56,7 +56,7 @@ constexpr double kCs2 = 1.0 / 3.0;
 // are at most kStripOut).  Automatic choice: the longest segment (fewest
 // recomputed halo rows) that still gives kTargetItems work items, so that the
 // GPU stays full through the tail of a launch; the shortest otherwise.
-constexpr int kSegCandidates[] = {128, 96, 80, 72, 64, 56, 48, 40, 32, 24, 16};
+constexpr int kSegCandidates[] = {128, 96, 80, 72, 64, 56, 48, 40, 32, 24, 16, 8};
 constexpr int kMinSegRows = 8;
 constexpr int kTargetItems = 4096;
 constexpr int kXcds = 8;   // MI355X: workgroups are dealt to the 8 XCDs in turn
@@ -141,8 +141,9 @@ int units_per_step(const ifdlbm_s* h) { return h->opt.kernel == IFDLBM_KERNEL_ST
 // nearest row that is 4 (mod 5).  The fused kernel's march then starts at a
 // row that is 0 (mod 5), so every row is computed by the same unrolled copy
 // of the row code whatever the segmentation, and results do not depend on
-// the composition of the batch.  Segments of >= 16 rows move by <= 2 rows at
-// each end and keep >= 4 rows.
+// the composition of the batch.  Each end moves by <= 2 rows; with >= 8 rows
+// per segment the interior segments keep a multiple of 5 rows and the two end
+// segments >= 4 (checked for every ny up to 4000).
 int segment_start(int g, int ng, int ny)
 {
     if (g <= 0) return 0;
@@ -502,8 +503,8 @@ static int ifdlbm_create_impl(const ifdlbm_cavity* cav, int32_t n_cav, const ifd
         return fail(IFDLBM_EINVAL, "graph_steps must be 0, or even and a multiple of residual_every");
     if (o.lambda_mode != IFDLBM_LAMBDA_LAGGED && o.lambda_mode != IFDLBM_LAMBDA_IMPLICIT)
         return fail(IFDLBM_EINVAL, "unknown lambda_mode");
-    if (o.segment_rows != 0 && (o.segment_rows < 16 || o.segment_rows > 4096))
-        return fail(IFDLBM_EINVAL, "segment_rows must be 0 (automatic) or in [16, 4096]");
+    if (o.segment_rows != 0 && (o.segment_rows < 8 || o.segment_rows > 4096))
+        return fail(IFDLBM_EINVAL, "segment_rows must be 0 (automatic) or in [8, 4096]");
     for (int c = 0; c < n_cav; ++c) {
         const ifdlbm_cavity& v = cav[c];
         const std::string id = "cavity " + std::to_string(c) + ": ";

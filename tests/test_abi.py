@@ -65,7 +65,7 @@ def test_create_rejects_bad_cavity(cav):
 
 @pytest.mark.parametrize("field,value", [("cfl", 0.0), ("mix", 1.5), ("gamma_min", 0.0), ("residual_every", 0),
                                          ("precision", 7), ("kernel", 9), ("graph_steps", 3),
-                                         ("segment_rows", 15), ("segment_rows", 5000), ("dt_rule", 2),
+                                         ("segment_rows", 7), ("segment_rows", 5000), ("dt_rule", 2),
                                          ("lambda_mode", 2)])
 def test_create_rejects_bad_options(field, value):
     o = M.ifdlbm_default_options(**{field: value})

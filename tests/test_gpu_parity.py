@@ -425,7 +425,7 @@ def test_batch_equals_single_cavity_runs(kernel, precision):
         assert np.array_equal(F, F1) and np.array_equal(L, L1), c
 
 
-@pytest.mark.parametrize("rows", [16, 24, 64, 4096])
+@pytest.mark.parametrize("rows", [8, 16, 24, 64, 4096])
 def test_fused_segmentation_does_not_change_results(rows):
     """FP32 fused kernel with forced segment lengths: bitwise equal to the
     automatic choice."""
@@ -447,7 +447,7 @@ def test_autotune_keeps_state_and_results(precision):
     h = gpu(specs, 20, precision, "fused")
     rows, ms = M.ifdlbm_autotune(h, 5)
     print(precision, rows, ms, flush=True)
-    assert rows in (16, 24, 32, 40, 48, 56, 64, 72, 80, 96, 128) and ms > 0.0
+    assert rows in (8, 16, 24, 32, 40, 48, 56, 64, 72, 80, 96, 128) and ms > 0.0
     M.ifdlbm_step(h, 15)
     for c in range(2):
         a, b = M.ifdlbm_get_state(ref, c), M.ifdlbm_get_state(h, c)
