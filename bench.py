@@ -264,7 +264,11 @@ def main() -> int:
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_record(args.precision, "bytes", seg_rows),
                      "kernel_ms": kernel_ms, "alg_bytes_per_launch": alg_bytes,
-                     "alg_bytes_per_node": info["alg_bytes_per_node"], "valu": valu},
+                     "alg_bytes_per_node": info["alg_bytes_per_node"], "valu": valu,
+                     # the limit the kernel runs into: the larger of the HBM fraction (the metric's) and the VALU
+                     # issue fraction of the same launches (None without the counter record)
+                     "binding": (None if valu is None else
+                                 ("valu" if valu["frac"] > achieved / HBM_PEAK_GBS else "hbm"))},
         "fp64_plain": plain,
         "other_fp32_storage_modes": other or None,
         "speedup_vs_fp64_plain": (mlups / plain["value"]) if plain else None,
