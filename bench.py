@@ -85,6 +85,15 @@ def measured_record(precision: str, what: str, segment_rows):
     return float(rec[key]) if key in rec else None
 
 
+def binding_limit(hbm_frac: float, valu):
+    """The limit the kernel runs into: "valu" when the VALU issue fraction of the
+    same launches exceeds the HBM fraction (the metric's), else "hbm"; None
+    without a VALU figure."""
+    if not valu:
+        return None
+    return "valu" if valu["frac"] > hbm_frac else "hbm"
+
+
 def time_steps(M, h, stream, steps: int, warmup: int):
     import torch
     M.ifdlbm_step(h, warmup)
@@ -265,10 +274,7 @@ def main() -> int:
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_record(args.precision, "bytes", seg_rows),
                      "kernel_ms": kernel_ms, "alg_bytes_per_launch": alg_bytes,
                      "alg_bytes_per_node": info["alg_bytes_per_node"], "valu": valu,
-                     # the limit the kernel runs into: the larger of the HBM fraction (the metric's) and the VALU
-                     # issue fraction of the same launches (None without the counter record)
-                     "binding": (None if valu is None else
-                                 ("valu" if valu["frac"] > achieved / HBM_PEAK_GBS else "hbm"))},
+                     "binding": binding_limit(achieved / HBM_PEAK_GBS, valu)},
         "fp64_plain": plain,
         "other_fp32_storage_modes": other or None,
         "speedup_vs_fp64_plain": (mlups / plain["value"]) if plain else None,

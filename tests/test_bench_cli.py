@@ -23,3 +23,11 @@ def test_kernel_source_digest():
     assert any(p.endswith("step_fused.hip") for p in bench.KERNEL_SOURCES)
     assert bench.measured_record("no-such-precision", "bytes", 48) is None
     assert bench.measured_record("fp32srf", "bytes", None) is None
+
+
+def test_binding_limit():
+    sys.path.insert(0, ROOT)
+    import bench
+    assert bench.binding_limit(0.31, {"frac": 0.71}) == "valu"
+    assert bench.binding_limit(0.80, {"frac": 0.40}) == "hbm"
+    assert bench.binding_limit(0.31, None) is None
