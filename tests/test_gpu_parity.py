@@ -425,13 +425,15 @@ def test_batch_equals_single_cavity_runs(kernel, precision):
         assert np.array_equal(F, F1) and np.array_equal(L, L1), c
 
 
-@pytest.mark.parametrize("rows", [8, 16, 24, 64, 4096])
-def test_fused_segmentation_does_not_change_results(rows):
-    """FP32 fused kernel with forced segment lengths: bitwise equal to the
-    automatic choice."""
+@pytest.mark.parametrize("precision", ["fp32", "fp32srf", "fp16dev"])
+@pytest.mark.parametrize("rows", [0, 8, 24, 64, 4096])
+def test_fused_segmentation_does_not_change_results(rows, precision):
+    """Fused kernel with other segment lengths (0: the automatic choice): bitwise
+    equal to 16-row segments, in the storage modes with round-to-nearest, with
+    the exact final update and with FP16 stochastic rounding."""
     specs = [W.CavitySpec(129, 129, 400.0, 0.8, 60.0), W.CavitySpec(65, 97, 1000.0, 1.3, 45.0)]
-    ref = gpu(specs, 30, "fp32", "fused")
-    h = gpu(specs, 30, "fp32", "fused", segment_rows=rows)
+    ref = gpu(specs, 30, precision, "fused", segment_rows=16)
+    h = gpu(specs, 30, precision, "fused", segment_rows=rows)
     for c in range(2):
         a, b = M.ifdlbm_get_state(ref, c), M.ifdlbm_get_state(h, c)
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), c
