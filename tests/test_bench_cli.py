@@ -31,3 +31,21 @@ def test_binding_limit():
     assert bench.binding_limit(0.31, {"frac": 0.71}) == "valu"
     assert bench.binding_limit(0.80, {"frac": 0.40}) == "hbm"
     assert bench.binding_limit(0.31, None) is None
+
+
+def test_counter_record_covers_the_autotuner_choices():
+    """The committed counter record holds positive HBM bytes and VALU instructions per launch for every
+    benchmarked storage mode at 32 to 80 rows, the segment lengths the autotuner picks on the batch."""
+    sys.path.insert(0, ROOT)
+    import bench
+    rec = {}
+    with open(bench.TRAFFIC_RECORD) as f:
+        for line in f:
+            if ":" in line and not line.startswith(" "):
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip()
+    assert len(rec["kernel_sources_sha256"]) == 64
+    for prec in ("fp32srf", "fp32", "fp64"):
+        for seg in range(32, 81, 8):
+            for what in ("bytes", "valu_insts"):
+                assert float(rec["%s_per_launch_%s_seg%d" % (what, prec, seg)]) > 0, (what, prec, seg)
