@@ -3,15 +3,20 @@
 Workload (one "step" = one time step of every cavity): the seeded batch of
 256 lid-driven isosceles-trapezoid cavities of uneven size and parameters
 (sides 65/129/257/513, Re 100-5000 log-uniform, n 0.5-1.5, theta 40-90 deg,
-lid 0.1, CFL 0.5), FP32 storage of the distributions with stochastic
-rounding and FP64 arithmetic by default (--precision selects the other
-modes), FP64 residual sums of Eq. (2.19) every 100 steps, all cavities in one
-launch per step, replayed from a captured HIP graph.  Inputs start resident in HBM (Step 1 on the
-device).  Printed on one JSON line: MLUPS, the roofline record of the step
-kernel (algorithmic bytes per launch over its average duration, from HIP
+lid 0.1, CFL 0.5).  By default the distributions are stored in FP32 with
+stochastic rounding and updated in FP32 arithmetic, with the final sum of
+each update in FP64 (--precision selects the other modes); FP64 residual sums
+of Eq. (2.19) every 100 steps; all cavities in one launch per step, replayed
+from captured HIP graphs of 100 steps.  With fewer than 100 timed steps the
+graph and the residual interval shrink to the timed count, so that the timed
+region is whole graph replays, each with one residual step; the JSON line
+records what the timed region ran.  Inputs start resident in HBM (Step 1 on
+the device).  Printed on one JSON line: MLUPS, the roofline record of the
+step kernel (algorithmic bytes per launch over its average duration, from HIP
 events on the stream the library launches on), the same batch in FP64 with
-one launch per cavity and no graph ("plain FP64", and the speedup over it),
-and the serial CPU oracle timed on a bounded sample of the batch.
+one launch per cavity and no graph ("plain FP64") and in one launch per step
+("batched FP64"), the speedups over both, the other storage modes, and the
+serial CPU oracle timed on a bounded sample of the batch.
 """
 from __future__ import annotations
 
@@ -29,8 +34,8 @@ METRIC = "MLUPS & % HBM roofline, FP32-batched vs plain FP64 on GPU at ≤1e-5 v
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, published
 VALU_PEAK_GINST = 256 * 4 * 2.4 / 4   # wave64 VALU instructions per ns: 256 CUs, 4 SIMD16 each, 2.4 GHz
 WORKLOAD = ("256-cavity uneven batch: sides {65,129,257,513}, Re log-uniform [100,5000], n uniform [0.5,1.5], "
-            "theta uniform [40,90] deg, lid 0.1, CFL 0.5, central weight 0.75; FP64 residual sums every 100 steps, "
-            "one launch per step, HIP-graph replay")
+            "theta uniform [40,90] deg, lid 0.1, CFL 0.5, central weight 0.75; one launch per step for all cavities; "
+            "timed: %s")
 # storage of the distributions and arithmetic type of each precision mode
 PRECISION = {
     "fp32srf": ("FP32, stochastic rounding; FP32 arithmetic, the final update of f-hat summed in FP64", "f32"),
@@ -152,6 +157,54 @@ def copy_calibration() -> int:
     return 0
 
 
+def timed_schedule(steps: int, warmup: int, graph_steps: int, residual_every: int):
+    """Graph size, residual interval and warm-up count of a run of `steps`
+    timed steps: with fewer timed steps than a graph holds, the graph and the
+    residual interval shrink to the timed count (rounded down to even, as the
+    library requires), and the warm-up rounds up to whole graphs, so that the
+    timed region starts at a graph boundary."""
+    if graph_steps > 0 and steps < graph_steps:
+        graph_steps = max(2, steps - steps % 2)
+        residual_every = graph_steps
+    if graph_steps > 0:
+        warmup = -(-warmup // graph_steps) * graph_steps
+    return graph_steps, residual_every, warmup
+
+
+def executed(start: int, steps: int, graph_steps: int, residual_every: int) -> dict:
+    """What ifdlbm_step(steps) runs from step count `start`: graph replays
+    cover whole graphs from a multiple of graph_steps, the rest is eager
+    launches; residual steps are those whose count is a multiple of
+    residual_every (the library's schedule)."""
+    G = graph_steps
+    lead = min((G - start % G) % G, steps) if G > 0 else steps
+    replays = (steps - lead) // G if G > 0 else 0
+    eager = steps - replays * G
+    residual = (start + steps) // residual_every - start // residual_every
+    return {"graph_replays": replays, "graph_steps": G, "eager_steps": eager, "residual_steps": residual,
+            "residual_every": residual_every}
+
+
+def describe(ex: dict) -> str:
+    parts = []
+    if ex["graph_replays"]:
+        parts.append("%d replays of a %d-step HIP graph" % (ex["graph_replays"], ex["graph_steps"]))
+    if ex["eager_steps"]:
+        parts.append("%d eager steps" % ex["eager_steps"])
+    parts.append("%d steps with the FP64 residual sums of Eq. (2.19)" % ex["residual_steps"])
+    return ", ".join(parts)
+
+
+def run_mode(M, cav, stream, prec: str, kernel: str, steps: int, warmup: int, **opt):
+    """MLUPS of `steps` steps of the batch in another mode (fresh handle)."""
+    o = M.ifdlbm_default_options(precision=prec, kernel=kernel, hip_stream=stream.cuda_stream, **opt)
+    h = M.ifdlbm_create(cav, o)
+    nodes = M.ifdlbm_info(h)["nodes"]
+    wall, _ = time_steps(M, h, stream, steps, warmup)
+    h.close()
+    return nodes * steps / wall / 1e6, wall * 1e3 / steps
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -167,7 +220,7 @@ def main() -> int:
                     help="force the fused kernel's row-segment length (skips the autotuner; for profiling runs)")
     ap.add_argument("--plain-steps", type=int, default=100, help="steps of the plain FP64 comparison run (0: skip)")
     ap.add_argument("--other-steps", type=int, default=300,
-                    help="steps of each other FP32-storage mode, reported beside the headline (0: skip)")
+                    help="steps of each other mode (batched FP64 and the other storage modes) (0: skip)")
     ap.add_argument("--cpu-steps", type=int, default=100, help="steps of the CPU oracle sample (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy three times (scale for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -195,17 +248,20 @@ def main() -> int:
     device = {"name": pr.name, "arch": getattr(pr, "gcnArchName", ""), "compute_units": pr.multi_processor_count,
               "memory_gib": round(pr.total_memory / 2**30, 1)}
 
-    opt = M.ifdlbm_default_options(precision=args.precision, kernel=args.kernel, residual_every=args.residual_every,
-                                   graph_steps=args.graph_steps, batched=1, hip_stream=stream.cuda_stream,
+    graph_steps, residual_every, warmup_run = timed_schedule(args.steps, args.warmup, args.graph_steps,
+                                                             args.residual_every)
+    opt = M.ifdlbm_default_options(precision=args.precision, kernel=args.kernel, residual_every=residual_every,
+                                   graph_steps=graph_steps, batched=1, hip_stream=stream.cuda_stream,
                                    segment_rows=args.segment_rows)
     h = M.ifdlbm_create(cav, opt)
     seg_rows = args.segment_rows or None
-    if args.autotune_steps > 0 and not args.segment_rows:
+    if args.autotune_steps > 0 and not args.segment_rows and args.kernel == "fused":
         seg_rows, tuned_ms = M.ifdlbm_autotune(h, args.autotune_steps)
         log("autotune: %d-row segments, %.3f ms/step in its trials" % (seg_rows, tuned_ms))
     info = M.ifdlbm_info(h)
     log("created %d cavities, %d nodes per step, %d work items" % (info["n_cavities"], info["nodes"], info["work_items"]))
-    wall, ev_ms = time_steps(M, h, stream, args.steps, args.warmup)
+    ex = executed(warmup_run, args.steps, graph_steps, residual_every)   # the autotuner restores the step count
+    wall, ev_ms = time_steps(M, h, stream, args.steps, warmup_run)
     ru, rp = M.ifdlbm_get_residuals(h)
     import numpy as np
     bad = [int(c) for c in np.nonzero(~(np.isfinite(ru) & np.isfinite(rp)))[0]]
@@ -217,10 +273,14 @@ def main() -> int:
     nodes = info["nodes"]
     mlups = nodes * args.steps / wall / 1e6
     launches = args.steps * info["launches_per_step"]
+    # HIP-event time of the timed region per launch of the step kernel: it also holds the one-thread seed kernel
+    # of each graph replay or eager call and the residual reduction of each residual step (a few microseconds
+    # against hundreds per launch)
     kernel_ms = ev_ms / launches
     alg_bytes = nodes * info["alg_bytes_per_node"]
     achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
-    log(args.precision + " batched: %.1f MLUPS, %.3f ms/step, kernel %.3f ms, %.0f GB/s" % (mlups, wall * 1e3 / args.steps, kernel_ms, achieved))
+    log(args.precision + " batched: %.1f MLUPS, %.3f ms/step, %.3f ms per launch (events), %.0f GB/s; timed: %s" % (
+        mlups, wall * 1e3 / args.steps, kernel_ms, achieved, describe(ex)))
     # the vector-ALU issue rate of the same launches: SQ_INSTS_VALU per launch (counter record) over the
     # measured launch time, against 256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per wave64 instruction
     insts = measured_record(args.precision, "valu_insts", seg_rows)
@@ -233,51 +293,52 @@ def main() -> int:
 
     plain = None
     if args.plain_steps > 0:
-        opt64 = M.ifdlbm_default_options(precision="fp64", kernel=args.kernel, residual_every=args.residual_every,
-                                         graph_steps=0, batched=0, hip_stream=stream.cuda_stream)
-        h64 = M.ifdlbm_create(cav, opt64)
-        wall64, ev64 = time_steps(M, h64, stream, args.plain_steps, min(args.warmup, 20))
-        mlups64 = nodes * args.plain_steps / wall64 / 1e6
-        plain = {"value": mlups64, "unit": "MLUPS", "ms_per_step": wall64 * 1e3 / args.plain_steps,
-                 "steps": args.plain_steps, "config": "same batch, FP64, one launch per cavity per step, no graph"}
-        log("fp64 plain: %.1f MLUPS" % mlups64)
-        h64.close()
+        # FP64, one launch per cavity and per step, no graph; each cavity's launch takes the row-segment length
+        # that fills the GPU with that cavity alone (the library's rule for unbatched launches)
+        v64, ms64 = run_mode(M, cav, stream, "fp64", args.kernel, args.plain_steps, min(args.warmup, 20),
+                             residual_every=residual_every, graph_steps=0, batched=0)
+        plain = {"value": v64, "unit": "MLUPS", "ms_per_step": ms64, "steps": args.plain_steps,
+                 "config": "same batch, FP64, one launch per cavity per step with its own segment length, no graph"}
+        log("fp64 plain: %.1f MLUPS" % v64)
 
     other = {}
     if args.other_steps > 0:
-        for prec in ("fp32srf", "fp32sr", "fp32"):
+        for prec in ("fp64", "fp32srf", "fp32sr", "fp32", "fp16dev"):
             if prec == args.precision:
                 continue
-            o2 = M.ifdlbm_default_options(precision=prec, kernel=args.kernel, residual_every=args.residual_every,
-                                          graph_steps=args.graph_steps, batched=1, hip_stream=stream.cuda_stream)
-            h2 = M.ifdlbm_create(cav, o2)
-            w2, e2 = time_steps(M, h2, stream, args.other_steps, min(args.warmup, 50))
-            other[prec] = {"value": nodes * args.other_steps / w2 / 1e6, "unit": "MLUPS",
-                           "storage": PRECISION[prec][0], "dtype": PRECISION[prec][1], "steps": args.other_steps}
-            log("%s batched: %.1f MLUPS" % (prec, other[prec]["value"]))
-            h2.close()
+            gs, re_, wu = timed_schedule(args.other_steps, min(args.warmup, 50), args.graph_steps, args.residual_every)
+            v, ms = run_mode(M, cav, stream, prec, args.kernel, args.other_steps, wu, residual_every=re_,
+                             graph_steps=gs, batched=1)
+            other[prec] = {"value": v, "unit": "MLUPS", "ms_per_step": ms, "storage": PRECISION[prec][0],
+                           "dtype": PRECISION[prec][1], "steps": args.other_steps,
+                           "alg_bytes_per_node": {"fp64": 160.0, "fp16dev": 44.0}.get(prec, 80.0)}
+            log("%s batched: %.1f MLUPS" % (prec, v))
 
     cpu = cpu_baseline(specs, args.cpu_steps) if args.cpu_steps > 0 else None
     if cpu:
         log("cpu oracle: %.3f MLUPS" % cpu["value"])
 
+    fp64_batched = other.get("fp64")
     out = {
         "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": PRECISION[args.precision][1], "data": "synthetic",
-        "config": {"workload": WORKLOAD, "cavities": len(specs), "nodes_per_step": nodes, "kernel": args.kernel,
-                   "precision": args.precision, "storage": PRECISION[args.precision][0],
-                   "diverged_cavities": diverged, "diverged_indices": bad,
-                   "residual_every": args.residual_every, "graph_steps": args.graph_steps,
-                   "segment_rows": seg_rows, "autotune_steps": args.autotune_steps},
+        "config": {"workload": WORKLOAD % describe(ex), "cavities": len(specs), "nodes_per_step": nodes,
+                   "kernel": args.kernel, "precision": args.precision, "storage": PRECISION[args.precision][0],
+                   "diverged_cavities": diverged, "diverged_indices": bad, "warmup_steps_run": warmup_run,
+                   "segment_rows": seg_rows, "autotune_steps": args.autotune_steps, **ex},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_record(args.precision, "bytes", seg_rows),
-                     "kernel_ms": kernel_ms, "alg_bytes_per_launch": alg_bytes,
+                     "traffic_counters": "FETCH_SIZE + WRITE_SIZE per launch, scaled by a plain copy: bytes between "
+                                         "L2 and the memory fabric, Infinity Cache hits included",
+                     "event_ms_per_launch": kernel_ms, "alg_bytes_per_launch": alg_bytes,
                      "alg_bytes_per_node": info["alg_bytes_per_node"], "valu": valu,
                      "binding": binding_limit(achieved / HBM_PEAK_GBS, valu)},
         "fp64_plain": plain,
-        "other_fp32_storage_modes": other or None,
+        "fp64_batched": fp64_batched,
+        "other_modes": other or None,
         "speedup_vs_fp64_plain": (mlups / plain["value"]) if plain else None,
+        "speedup_vs_fp64_batched": (mlups / fp64_batched["value"]) if fp64_batched else None,
         "cpu_baseline": cpu,
         "device": device,
     }

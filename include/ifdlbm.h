@@ -10,10 +10,12 @@
  * mixed-difference streaming on the body-fitted grid (Eqs. 3.7, 2.5-2.7,
  * 3.2-3.8.2) with f(t+dt/2) from Eq. (2.17), full-step streaming (Eq. 3.6),
  * and non-equilibrium-extrapolation walls and lid (Eq. 1.5).  Step (8), the
- * global relative error of Eq. (2.19), is evaluated every residual_every steps;
- * its E(P) is taken on the pressure with the spatial mean removed (the level
- * of P is a gauge of the incompressible model, and the extrapolation walls
- * let it drift at a constant rate once u is steady).
+ * global relative errors of Eq. (2.19), is evaluated every residual_every
+ * steps.  E(P) comes in two forms: as printed, and on the pressure with its
+ * spatial mean removed (the default for the steady-state test: the level of P
+ * is a gauge of the incompressible model, and the extrapolation walls let it
+ * drift at a constant rate once u is steady, so the printed form then decays
+ * only like 1/steps).
  *
  * Conventions for every call:
  *  - Return 0 (IFDLBM_OK) on success or a negative IFDLBM_E* code.  No C++
@@ -25,8 +27,9 @@
  *  - Host arrays of one cavity are row-major [j][i] with i (xi, along the
  *    lid) fastest: n_eta rows of n_xi values.  Distribution arrays are
  *    [k][j][i], k = 0..8 in the order of Eq. (2.9).
- *  - Work is enqueued on the handle's HIP stream (options.hip_stream, or the
- *    null stream).  Calls that return host data synchronise that stream.
+ *  - Work is enqueued on the handle's HIP stream: options.hip_stream, or with
+ *    NULL a non-blocking stream that the handle creates and owns.  Calls that
+ *    return host data synchronise that stream.
  *  - A handle must not be used by two threads at once.
  */
 #ifndef IFDLBM_H
@@ -80,6 +83,10 @@ typedef struct ifdlbm_s ifdlbm_t;
                                       strain rate taken at that lambda (safeguarded Newton iteration);
                                       steady states are those of the lagged scheme                      */
 
+/* E(P) of Eq. (2.19) that the steady-state test uses (options.pressure_residual) */
+#define IFDLBM_EP_MEAN_REMOVED  0  /* pressure deviations from their spatial mean (default)             */
+#define IFDLBM_EP_PRINTED       1  /* Eq. (2.19) as printed: sqrt(sum (P_new - P_old)^2 / sum P_new^2)  */
+
 /* cavity status (ifdlbm_status) */
 #define IFDLBM_STATUS_RUNNING       0
 #define IFDLBM_STATUS_CONVERGED     1
@@ -109,7 +116,8 @@ typedef struct {
     int32_t dt_rule;        /* IFDLBM_DT_CONTRAVARIANT | IFDLBM_DT_CARTESIAN                          */
     int32_t segment_rows;   /* fused kernel: rows per work item, 0 = automatic, else in [8, 4096]     */
     int32_t lambda_mode;    /* IFDLBM_LAMBDA_LAGGED (the paper's, default) | IFDLBM_LAMBDA_IMPLICIT    */
-    void*   hip_stream;     /* hipStream_t to enqueue on, or NULL for the null stream                 */
+    int32_t pressure_residual; /* IFDLBM_EP_MEAN_REMOVED (default) | IFDLBM_EP_PRINTED                  */
+    void*   hip_stream;     /* hipStream_t to enqueue on, or NULL: the handle creates its own         */
 } ifdlbm_options;
 
 /* Sizes of a handle's work, for throughput and roofline accounting. */
@@ -125,7 +133,7 @@ typedef struct {
 
 /* Fills *opt with the defaults: FP64, cfl 0.5, mix 0.75, rho0 1, gamma_min 1e-6, residual_every 1,
    fused kernel, batched, no graph, contravariant time-step rule, automatic segment rows, lagged lambda,
-   null stream. */
+   mean-removed E(P), a stream of the handle's own (hip_stream NULL). */
 int ifdlbm_default_options(ifdlbm_options* opt);
 
 /* Validates cav[0..n_cav) and *opt, builds the metric terms of Eqs. (3.2)-(3.8.2) in FP64 on the host,
@@ -145,7 +153,8 @@ int ifdlbm_step(ifdlbm_t* h, int64_t n_steps);
 /* Waits for all enqueued work of the handle. */
 int ifdlbm_sync(ifdlbm_t* h);
 
-/* Steps until both global relative errors E(u), E(P) of Eq. (2.19) are <= tol for every cavity, or
+/* Steps until both global relative errors E(u), E(P) of Eq. (2.19) (E(P) in the form options.pressure_residual
+   selects) are <= tol for every cavity, or
    max_steps more steps were taken.  Converged cavities stop stepping (status CONVERGED); a cavity whose
    state becomes non-finite stops (status DIVERGED) while the others continue.  steps_done, res_u and
    res_p are caller-owned arrays of n_cav entries (any may be NULL) receiving, per cavity, the steps taken
@@ -154,17 +163,28 @@ int ifdlbm_sync(ifdlbm_t* h);
 int ifdlbm_run_to_steady(ifdlbm_t* h, double tol, int64_t max_steps,
                          int64_t* steps_done, double* res_u, double* res_p);
 
-/* Last evaluated residuals E(u), E(P) of Eq. (2.19) for every cavity (arrays of n_cav, caller-owned).  A running
-   cavity whose residual sums are non-finite is marked IFDLBM_STATUS_DIVERGED here and stops stepping; the
-   others continue (its residuals read NaN). */
+/* Last evaluated residuals E(u), E(P) of Eq. (2.19) for every cavity (arrays of n_cav, caller-owned, either may
+   be NULL), E(P) in the form options.pressure_residual selects.  A running cavity whose residual sums are
+   non-finite is marked IFDLBM_STATUS_DIVERGED here and stops stepping; the others continue (its residuals read
+   NaN).  The sums are FP64, accumulated in a fixed order (deterministic).  The mean-removed E(P) comes from
+   sums of P and of P_new - P_old shifted by their means at the previous evaluation; a value below the
+   rounding bound of those sums (about 6e-14 of the shifted sum of squares) is reported as that bound, never as
+   zero. */
 int ifdlbm_get_residuals(ifdlbm_t* h, double* res_u, double* res_p);
+
+/* Both forms of E(P) of Eq. (2.19) from the same last evaluation, for every cavity (arrays of n_cav,
+   caller-owned, either may be NULL): as printed, sqrt(sum (P_new - P_old)^2) / sqrt(sum P_new^2) over all
+   nodes, and on the pressure with its spatial mean removed (see ifdlbm_get_residuals).  Marks non-finite
+   cavities DIVERGED as ifdlbm_get_residuals does.  Errors: EINVAL, EDEVICE. */
+int ifdlbm_get_pressure_residuals(ifdlbm_t* h, double* res_p_printed, double* res_p_mean_removed);
 
 /* Velocity (u, v) and pressure P of Eqs. (2.10)-(2.11) of cavity cav, FP64, into caller-owned host
    arrays of n_eta * n_xi values each (any may be NULL). */
 int ifdlbm_get_fields(ifdlbm_t* h, int32_t cav, double* u, double* v, double* p);
 
-/* As ifdlbm_get_fields, into caller-owned device arrays (dtype 0: float64, 1: float32), enqueued on the
-   handle's stream without waiting. */
+/* As ifdlbm_get_fields, into caller-owned device arrays (dtype 0: float64, 1: float32).  With a caller stream
+   (options.hip_stream) the copy is enqueued on it without waiting: the caller orders its own use of the arrays
+   after it.  With the handle's own stream the call waits until the arrays are written. */
 int ifdlbm_get_fields_device(ifdlbm_t* h, int32_t cav, void* u, void* v, void* p, int32_t dtype);
 
 /* Kinetic energy of Eq. (5.1) of cavity cav: 1/2 sum |u|^2 over the physical area, trapezoid weights in

@@ -5,6 +5,7 @@
 #include "ifdlbm.h"
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -106,12 +107,12 @@ struct ifdlbm_s {
     StripItem* d_act_items = nullptr;
     std::vector<StripItem> act_sorted;     // the same items, longest first (batched launch)
     StripItem* d_act_sorted = nullptr;
-    int seg_rows = 0;
     size_t max_units = 0;
     std::vector<int32_t> unit_first, unit_count;   // per cavity, in the active unit list
     int32_t *d_unit_first = nullptr, *d_unit_count = nullptr;
     double* d_partial = nullptr;
-    double* d_res = nullptr;                        // n_cav * kPartials
+    double* d_res = nullptr;                        // n_cav * kResult
+    double* d_ref = nullptr;                        // n_cav * 2 shifts of the residual sums
     double* d_scratch = nullptr;                    // 10 * max nodes doubles
     uint32_t* d_seed = nullptr;                     // stochastic-rounding step counter
     size_t scratch_elems = 0;
@@ -126,7 +127,7 @@ struct ifdlbm_s {
     int32_t *d_all_first = nullptr, *d_all_count = nullptr;
 
     std::vector<int> status;
-    std::vector<double> res_u, res_p;
+    std::vector<double> res_u, res_p_printed, res_p_gauge;   // last evaluated residuals of Eq. (2.19)
     int64_t step_count = 0;
     hipGraphExec_t graph_exec = nullptr;
     bool graph_dirty = true;
@@ -153,13 +154,16 @@ int segment_start(int g, int ng, int ny)
     return r <= 2 ? b - r : b + (5 - r);
 }
 
-int segment_rows(const ifdlbm_s* h)
+// Rows per segment for the cavities of one launch: all running cavities (one_cav < 0, batched launch) or
+// cavity one_cav alone (one launch per cavity).
+int segment_rows(const ifdlbm_s* h, int one_cav = -1)
 {
     if (h->opt.segment_rows > 0) return h->opt.segment_rows;
     for (int seg : kSegCandidates) {
         size_t n = 0;
         for (int c = 0; c < h->n_cav; ++c)
-            if (h->desc[c].active) n += (size_t)ceil_div(h->desc[c].ny, seg) * ceil_div(h->desc[c].nx, kStripOut);
+            if (h->desc[c].active && (one_cav < 0 || c == one_cav))
+                n += (size_t)ceil_div(h->desc[c].ny, seg) * ceil_div(h->desc[c].nx, kStripOut);
         if (n >= (size_t)kTargetItems) return seg;
     }
     return kSegCandidates[sizeof(kSegCandidates) / sizeof(kSegCandidates[0]) - 1];
@@ -217,10 +221,11 @@ int rebuild_worklists(ifdlbm_s* h)
 {
     h->act_blocks.clear();
     h->act_items.clear();
-    const int seg = segment_rows(h);
-    h->seg_rows = seg;
+    const int seg_batch = segment_rows(h);
     for (int c = 0; c < h->n_cav; ++c) {
         const bool run = h->desc[c].active != 0;
+        // a launch of its own fills the GPU only with the cavity's own segment length
+        const int seg = h->opt.batched ? seg_batch : segment_rows(h, c);
         if (h->opt.kernel == IFDLBM_KERNEL_STAGED) {
             h->unit_first[c] = (int32_t)h->act_blocks.size();
             if (run) {
@@ -272,6 +277,7 @@ StepArgs step_args(ifdlbm_s* h)
     a.geo = h->d_geo;
     a.geo32 = h->d_geo32;
     a.partial = h->d_partial;
+    a.res_ref = h->d_ref;
     a.hat_plus = h->d_hp;
     a.bar_plus = h->d_bp;
     a.bar_half = h->d_fb;
@@ -302,7 +308,8 @@ int enqueue_step(ifdlbm_s* h, bool residual, uint32_t local)
         }
     }
     if (e == hipSuccess && residual)
-        e = launch_reduce_partials(h->d_partial, h->d_unit_first, h->d_unit_count, h->n_cav, h->d_res, h->stream);
+        e = launch_reduce_partials(h->d_partial, h->d_unit_first, h->d_unit_count, h->d_desc, h->n_cav, h->d_ref, h->d_res,
+                                   h->stream);
     if (e != hipSuccess) return fail(IFDLBM_EDEVICE, std::string("step launch: ") + hipGetErrorString(e));
     return IFDLBM_OK;
 }
@@ -421,7 +428,7 @@ int check_cav(const ifdlbm_s* h, int32_t c)
 
 int read_residuals(ifdlbm_s* h, std::vector<double>& sums)
 {
-    sums.assign((size_t)h->n_cav * kPartials, 0.0);
+    sums.assign((size_t)h->n_cav * kResult, 0.0);
     IFD_HIP(hipMemcpyAsync(sums.data(), h->d_res, sums.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     IFD_HIP(hipStreamSynchronize(h->stream));
     return IFDLBM_OK;
@@ -429,14 +436,47 @@ int read_residuals(ifdlbm_s* h, std::vector<double>& sums)
 
 double rel(double num2, double den2) { return num2 <= 0.0 ? 0.0 : std::sqrt(num2) / std::sqrt(den2); }
 
-// Eq. (2.19) from the partial sums of one cavity of nn nodes: E(u), and E(P)
-// of the pressure with its spatial mean removed (sum (dP - mean dP)^2 =
-// sum dP^2 - (sum dP)^2 / nn, likewise for P).  Returns false if non-finite.
-bool residuals_of(const double* s, double nn, double& eu, double& ep)
+// Relative rounding error of the FP64 residual sums: each partial sums at most
+// a few hundred terms in order (a row segment per lane, a wavefront, the
+// units of a cavity), so |error| < 512 u of the sum of the magnitudes.
+constexpr double kSumRel = 512.0 * 0x1p-53;
+
+// Eq. (2.19) from the sums of one cavity of nn nodes (layout of kResult):
+// E(u); E(P) as printed; and E(P) of the pressure with its spatial mean
+// removed, from the shifted sums: sum (x - r)^2 - (sum (x - r))^2 / nn is the
+// sum of squared deviations from the mean.  A variance that the sums do not
+// resolve (below the rounding bound of the subtraction, kSumRel times the
+// shifted sum of squares) is reported as that bound: an upper limit, so that
+// rounding never reads as convergence.  Returns false if non-finite.
+bool residuals_of(const double* s, double nn, double& eu, double& ep_printed, double& ep_gauge)
 {
     eu = rel(s[0], s[1]);
-    ep = rel(s[2] - s[4] * s[4] / nn, s[3] - s[5] * s[5] / nn);
-    return s[6] == 0.0 && std::isfinite(eu) && std::isfinite(ep);
+    ep_printed = rel(s[2], s[3]);
+    const double num = s[7] - s[4] * s[4] / nn;
+    const double den = s[8] - s[5] * s[5] / nn;
+    const double floor = kSumRel * s[7];
+    if (den > 0.0)
+        ep_gauge = std::sqrt(num > floor ? num : floor) / std::sqrt(den);
+    else   // uniform pressure: 0/0 counts as 0; a resolved change of a uniform field is never converged
+        ep_gauge = num > floor ? DBL_MAX : 0.0;
+    return s[6] == 0.0 && std::isfinite(eu) && std::isfinite(ep_printed) && std::isfinite(ep_gauge);
+}
+
+// The E(P) that the handle's options.pressure_residual selects.
+double selected_ep(const ifdlbm_s* h, int c)
+{
+    return h->opt.pressure_residual == IFDLBM_EP_PRINTED ? h->res_p_printed[c] : h->res_p_gauge[c];
+}
+
+// Evaluates the residual record of running cavity c into the handle; false if non-finite.
+bool update_residuals(ifdlbm_s* h, const std::vector<double>& sums, int c)
+{
+    double eu, epp, epg;
+    const bool ok = residuals_of(&sums[(size_t)c * kResult], (double)h->desc[c].nx * h->desc[c].ny, eu, epp, epg);
+    h->res_u[c] = ok ? eu : NAN;
+    h->res_p_printed[c] = ok ? epp : NAN;
+    h->res_p_gauge[c] = ok ? epg : NAN;
+    return ok;
 }
 
 void free_all(ifdlbm_s* h)
@@ -444,7 +484,7 @@ void free_all(ifdlbm_s* h)
     if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
     void* ptrs[] = {h->d_f[0], h->d_f[1], h->d_l[0], h->d_l[1], h->d_desc, h->d_geo, h->d_geo32, h->d_hp, h->d_bp,
                     h->d_fb, h->d_ln, h->d_all_blocks, h->d_act_blocks, h->d_act_items, h->d_act_sorted, h->d_unit_first,
-                    h->d_unit_count, h->d_partial, h->d_res, h->d_scratch, h->d_seed, h->d_rec, h->d_rec_count,
+                    h->d_unit_count, h->d_partial, h->d_res, h->d_ref, h->d_scratch, h->d_seed, h->d_rec, h->d_rec_count,
                     h->d_probe_partial, h->d_all_first, h->d_all_count};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -483,6 +523,7 @@ int ifdlbm_default_options(ifdlbm_options* opt)
     opt->dt_rule = IFDLBM_DT_CONTRAVARIANT;
     opt->segment_rows = 0;
     opt->lambda_mode = IFDLBM_LAMBDA_LAGGED;
+    opt->pressure_residual = IFDLBM_EP_MEAN_REMOVED;
     opt->hip_stream = nullptr;
     return IFDLBM_OK;
 }
@@ -503,6 +544,8 @@ static int ifdlbm_create_impl(const ifdlbm_cavity* cav, int32_t n_cav, const ifd
         return fail(IFDLBM_EINVAL, "graph_steps must be 0, or even and a multiple of residual_every");
     if (o.lambda_mode != IFDLBM_LAMBDA_LAGGED && o.lambda_mode != IFDLBM_LAMBDA_IMPLICIT)
         return fail(IFDLBM_EINVAL, "unknown lambda_mode");
+    if (o.pressure_residual != IFDLBM_EP_MEAN_REMOVED && o.pressure_residual != IFDLBM_EP_PRINTED)
+        return fail(IFDLBM_EINVAL, "unknown pressure_residual");
     if (o.segment_rows != 0 && (o.segment_rows < 8 || o.segment_rows > 4096))
         return fail(IFDLBM_EINVAL, "segment_rows must be 0 (automatic) or in [8, 4096]");
     for (int c = 0; c < n_cav; ++c) {
@@ -527,7 +570,8 @@ static int ifdlbm_create_impl(const ifdlbm_cavity* cav, int32_t n_cav, const ifd
     h->desc.resize(n_cav);
     h->status.assign(n_cav, IFDLBM_STATUS_RUNNING);
     h->res_u.assign(n_cav, NAN);
-    h->res_p.assign(n_cav, NAN);
+    h->res_p_printed.assign(n_cav, NAN);
+    h->res_p_gauge.assign(n_cav, NAN);
     h->unit_first.assign(n_cav, 0);
     h->unit_count.assign(n_cav, 0);
 
@@ -621,7 +665,8 @@ static int ifdlbm_create_impl(const ifdlbm_cavity* cav, int32_t n_cav, const ifd
     if (!rc) rc = dalloc(&h->d_unit_first, n_cav * sizeof(int32_t));
     if (!rc) rc = dalloc(&h->d_unit_count, n_cav * sizeof(int32_t));
     if (!rc) rc = dalloc(&h->d_partial, h->max_units * kPartials * sizeof(double));
-    if (!rc) rc = dalloc(&h->d_res, (size_t)n_cav * kPartials * sizeof(double));
+    if (!rc) rc = dalloc(&h->d_res, (size_t)n_cav * kResult * sizeof(double));
+    if (!rc) rc = dalloc(&h->d_ref, (size_t)n_cav * 2 * sizeof(double));
     if (!rc) rc = dalloc(&h->d_scratch, h->scratch_elems * sizeof(double));
     if (!rc) rc = dalloc(&h->d_seed, sizeof(uint32_t));
     if (!rc) rc = dalloc(&h->d_all_first, n_cav * sizeof(int32_t));
@@ -638,7 +683,8 @@ static int ifdlbm_create_impl(const ifdlbm_cavity* cav, int32_t n_cav, const ifd
     if (e == hipSuccess) e = copy(h->d_desc, h->desc.data(), n_cav * sizeof(CavityDesc));
     if (e == hipSuccess) e = copy(h->d_all_first, h->all_first.data(), n_cav * sizeof(int32_t));
     if (e == hipSuccess) e = copy(h->d_all_count, h->all_count.data(), n_cav * sizeof(int32_t));
-    if (e == hipSuccess) e = hipMemsetAsync(h->d_res, 0, (size_t)n_cav * kPartials * sizeof(double), h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(h->d_res, 0, (size_t)n_cav * kResult * sizeof(double), h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(h->d_ref, 0, (size_t)n_cav * 2 * sizeof(double), h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(h->d_seed, 0, sizeof(uint32_t), h->stream);
     if (e == hipSuccess)
         e = launch_init(prec, h->d_f[0], h->d_l[0], h->d_desc, h->d_all_blocks, (int)h->all_blocks.size(), h->stream);
@@ -664,7 +710,9 @@ static int ifdlbm_sync_impl(ifdlbm_t* h)
     return IFDLBM_OK;
 }
 
-static int ifdlbm_get_residuals_impl(ifdlbm_t* h, double* res_u, double* res_p)
+// Reads the last residual sums and evaluates them for every running cavity; a running cavity whose sums are
+// non-finite is marked DIVERGED and stops stepping.  Copies the residuals of every cavity to the non-null arrays.
+static int residuals_now(ifdlbm_t* h, double* res_u, double* res_p, double* res_p_printed, double* res_p_gauge)
 {
     if (!h) return fail(IFDLBM_EINVAL, "null handle");
     std::vector<double> sums;
@@ -672,24 +720,31 @@ static int ifdlbm_get_residuals_impl(ifdlbm_t* h, double* res_u, double* res_p)
     if (rc) return rc;
     bool changed = false;
     for (int c = 0; c < h->n_cav; ++c) {
-        if (h->desc[c].active) {
-            double eu, ep;
-            const bool ok = residuals_of(&sums[(size_t)c * kPartials], (double)h->desc[c].nx * h->desc[c].ny, eu, ep);
-            h->res_u[c] = ok ? eu : NAN;
-            h->res_p[c] = ok ? ep : NAN;
-            if (!ok) {   // non-finite state: the cavity stops stepping, the others continue
-                h->status[c] = IFDLBM_STATUS_DIVERGED;
-                h->desc[c].active = 0;
-                rc = mirror_state(h, c);
-                if (rc) return rc;
-                changed = true;
-            }
+        if (h->desc[c].active && !update_residuals(h, sums, c)) {
+            // non-finite state: the cavity stops stepping, the others continue
+            h->status[c] = IFDLBM_STATUS_DIVERGED;
+            h->desc[c].active = 0;
+            rc = mirror_state(h, c);
+            if (rc) return rc;
+            changed = true;
         }
         if (res_u) res_u[c] = h->res_u[c];
-        if (res_p) res_p[c] = h->res_p[c];
+        if (res_p) res_p[c] = selected_ep(h, c);
+        if (res_p_printed) res_p_printed[c] = h->res_p_printed[c];
+        if (res_p_gauge) res_p_gauge[c] = h->res_p_gauge[c];
     }
     if (changed) return rebuild_worklists(h);
     return IFDLBM_OK;
+}
+
+static int ifdlbm_get_residuals_impl(ifdlbm_t* h, double* res_u, double* res_p)
+{
+    return residuals_now(h, res_u, res_p, nullptr, nullptr);
+}
+
+static int ifdlbm_get_pressure_residuals_impl(ifdlbm_t* h, double* res_p_printed, double* res_p_mean_removed)
+{
+    return residuals_now(h, nullptr, nullptr, res_p_printed, res_p_mean_removed);
 }
 
 static int ifdlbm_run_to_steady_impl(ifdlbm_t* h, double tol, int64_t max_steps, int64_t* steps_done, double* res_u, double* res_p)
@@ -720,14 +775,11 @@ static int ifdlbm_run_to_steady_impl(ifdlbm_t* h, double tol, int64_t max_steps,
         bool changed = false;
         for (int c = 0; c < h->n_cav; ++c) {
             if (!h->desc[c].active) continue;
-            double eu, ep;
-            const bool ok = residuals_of(&sums[(size_t)c * kPartials], (double)h->desc[c].nx * h->desc[c].ny, eu, ep);
-            h->res_u[c] = ok ? eu : NAN;
-            h->res_p[c] = ok ? ep : NAN;
+            const bool ok = update_residuals(h, sums, c);
             int st = IFDLBM_STATUS_RUNNING;
             if (!ok)
                 st = IFDLBM_STATUS_DIVERGED;
-            else if (eu <= tol && ep <= tol)
+            else if (h->res_u[c] <= tol && selected_ep(h, c) <= tol)
                 st = IFDLBM_STATUS_CONVERGED;
             if (st != IFDLBM_STATUS_RUNNING) {
                 h->status[c] = st;
@@ -751,7 +803,7 @@ static int ifdlbm_run_to_steady_impl(ifdlbm_t* h, double tol, int64_t max_steps,
         }
         if (steps_done) steps_done[c] = done[c];
         if (res_u) res_u[c] = h->res_u[c];
-        if (res_p) res_p[c] = h->res_p[c];
+        if (res_p) res_p[c] = selected_ep(h, c);
     }
     IFD_HIP(hipStreamSynchronize(h->stream));
     if (diverged) return fail(IFDLBM_EDIVERGED, "a cavity diverged");
@@ -766,6 +818,8 @@ static int ifdlbm_get_fields_device_impl(ifdlbm_t* h, int32_t cav, void* u, void
     if (dtype != 0 && dtype != 1) return fail(IFDLBM_EINVAL, "dtype must be 0 (float64) or 1 (float32)");
     hipError_t e = launch_fields(h->opt.precision, h->d_f[h->cur], h->d_desc, cav, h->desc[cav], u, v, p, dtype, h->stream);
     if (e != hipSuccess) return fail(IFDLBM_EDEVICE, std::string("fields: ") + hipGetErrorString(e));
+    // the caller cannot order its own work after a stream it does not know
+    if (h->own_stream) IFD_HIP(hipStreamSynchronize(h->stream));
     return IFDLBM_OK;
 }
 
@@ -833,6 +887,8 @@ static int ifdlbm_set_state_impl(ifdlbm_t* h, int32_t cav, const double* fhat, c
         hipError_t e = launch_state_in(h->opt.precision, h->d_f[b], h->d_l[b], d, h->opt.rho0, s, s + 9 * nn, h->stream);
         if (e != hipSuccess) return fail(IFDLBM_EDEVICE, std::string("state in: ") + hipGetErrorString(e));
     }
+    // the residual shifts of the old trajectory would still be exact, but far from the new means
+    IFD_HIP(hipMemsetAsync(h->d_ref + 2 * cav, 0, 2 * sizeof(double), h->stream));
     IFD_HIP(hipStreamSynchronize(h->stream));
     h->status[cav] = IFDLBM_STATUS_RUNNING;
     if (!h->desc[cav].active) {
@@ -860,12 +916,13 @@ static int ifdlbm_autotune_impl(ifdlbm_t* h, int32_t steps_per_trial, int32_t* s
     // every trial starts from the current state, which is restored at the end
     const int prec = h->opt.precision;
     const size_t fb = h->f_elems * f_elem_size(prec), lb = h->l_elems * l_elem_size(prec);
-    const size_t rb = (size_t)h->n_cav * kPartials * sizeof(double);
-    void *bf = nullptr, *bl = nullptr, *br = nullptr;
+    const size_t rb = (size_t)h->n_cav * kResult * sizeof(double), qb = (size_t)h->n_cav * 2 * sizeof(double);
+    void *bf = nullptr, *bl = nullptr, *br = nullptr, *bq = nullptr;
     uint32_t* bs = nullptr;
     int rc = dalloc(&bf, fb);
     if (!rc) rc = dalloc(&bl, lb);
     if (!rc) rc = dalloc(&br, rb);
+    if (!rc) rc = dalloc(&bq, qb);
     if (!rc) rc = dalloc(&bs, sizeof(uint32_t));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
@@ -877,6 +934,7 @@ static int ifdlbm_autotune_impl(ifdlbm_t* h, int32_t steps_per_trial, int32_t* s
         hipError_t e = hipMemcpyAsync(bf, h->d_f[cur0], fb, hipMemcpyDeviceToDevice, h->stream);
         if (e == hipSuccess) e = hipMemcpyAsync(bl, h->d_l[cur0], lb, hipMemcpyDeviceToDevice, h->stream);
         if (e == hipSuccess) e = hipMemcpyAsync(br, h->d_res, rb, hipMemcpyDeviceToDevice, h->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(bq, h->d_ref, qb, hipMemcpyDeviceToDevice, h->stream);
         if (e == hipSuccess) e = hipMemcpyAsync(bs, h->d_seed, sizeof(uint32_t), hipMemcpyDeviceToDevice, h->stream);
         return e;
     };
@@ -884,6 +942,7 @@ static int ifdlbm_autotune_impl(ifdlbm_t* h, int32_t steps_per_trial, int32_t* s
         hipError_t e = hipMemcpyAsync(h->d_f[cur0], bf, fb, hipMemcpyDeviceToDevice, h->stream);
         if (e == hipSuccess) e = hipMemcpyAsync(h->d_l[cur0], bl, lb, hipMemcpyDeviceToDevice, h->stream);
         if (e == hipSuccess) e = hipMemcpyAsync(h->d_res, br, rb, hipMemcpyDeviceToDevice, h->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(h->d_ref, bq, qb, hipMemcpyDeviceToDevice, h->stream);
         if (e == hipSuccess) e = hipMemcpyAsync(h->d_seed, bs, sizeof(uint32_t), hipMemcpyDeviceToDevice, h->stream);
         h->cur = cur0;
         h->step_count = count0;
@@ -920,7 +979,7 @@ static int ifdlbm_autotune_impl(ifdlbm_t* h, int32_t steps_per_trial, int32_t* s
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     (void)hipStreamSynchronize(h->stream);
-    for (void* p : {bf, bl, br, static_cast<void*>(bs)})
+    for (void* p : {bf, bl, br, bq, static_cast<void*>(bs)})
         if (p) (void)hipFree(p);
     if (rc) return rc;
     if (rc2) return rc2;
@@ -1194,6 +1253,11 @@ int ifdlbm_sync(ifdlbm_t* h)
 int ifdlbm_get_residuals(ifdlbm_t* h, double* res_u, double* res_p)
 {
     IFD_GUARD(ifdlbm_get_residuals_impl(h, res_u, res_p));
+}
+
+int ifdlbm_get_pressure_residuals(ifdlbm_t* h, double* res_p_printed, double* res_p_mean_removed)
+{
+    IFD_GUARD(ifdlbm_get_pressure_residuals_impl(h, res_p_printed, res_p_mean_removed));
 }
 
 int ifdlbm_run_to_steady(ifdlbm_t* h, double tol, int64_t max_steps, int64_t* steps_done, double* res_u, double* res_p)

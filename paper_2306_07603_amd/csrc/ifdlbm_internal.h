@@ -34,11 +34,21 @@ struct StripItem {
     int32_t unit;   // slot of its residual partial sums (items of a cavity are consecutive slots)
 };
 
-// Residual partial sums of Eq. (2.19) per work unit: sum |u_new - u_old|^2,
-// sum |u_new|^2, sum (P_new - P_old)^2, sum P_new^2, sum (P_new - P_old),
-// sum P_new, count of non-finite nodes.  The two plain sums give E(P) of the
-// pressure with its spatial mean removed.
-constexpr int kPartials = 7;
+// Residual partial sums of Eq. (2.19) per work unit:
+//   0 sum |u_new - u_old|^2        1 sum |u_new|^2
+//   2 sum (P_new - P_old)^2        3 sum P_new^2          (E(P) as printed)
+//   4 sum (dP - r_d)               5 sum (P_new - r_p)
+//   6 count of non-finite nodes
+//   7 sum (dP - r_d)^2             8 sum (P_new - r_p)^2
+// with dP = P_new - P_old and per-cavity shifts r_d, r_p (the means found at
+// the previous evaluation).  Sums 4, 5, 7, 8 give E(P) of the pressure with
+// its spatial mean removed, sum (x - r)^2 - (sum (x - r))^2 / n per variance:
+// the shift keeps the subtraction from cancelling when the mean is far larger
+// than the spread, as the per-step change of a drifting pressure level is.
+constexpr int kPartials = 9;
+// Per-cavity record of a residual evaluation: the kPartials sums, then the
+// shifts r_d, r_p they were taken with.
+constexpr int kResult = kPartials + 2;
 
 struct StepArgs {
     const void* f_in;        // distributions, storage type, step start
@@ -49,6 +59,7 @@ struct StepArgs {
     const double* geo;       // metric tables a_j, s_i (FP64)
     const float* geo32;      // the same tables rounded to FP32
     double* partial;         // residual partials, kPartials per work unit
+    const double* res_ref;   // per-cavity shifts (r_d, r_p) of the residual sums
     // staged schedule only: temporaries in the arithmetic type
     void* hat_plus;          // f-hat+ (Eq. 2.15), 9 planes
     void* bar_plus;          // f-bar+ (Eq. 2.16), then f(t + dt/2) (Eq. 2.17), 9 planes
@@ -76,9 +87,11 @@ hipError_t launch_init(int prec, void* f, void* l, const CavityDesc* desc, const
                        hipStream_t s);
 
 // Per-cavity deterministic reduction of residual partials:
-// out[c * kPartials + q] = sum over units [first[c], first[c] + count[c]).
-hipError_t launch_reduce_partials(const double* partial, const int32_t* first, const int32_t* count, int n_cav,
-                                  double* out, hipStream_t s);
+// out[c * kResult + q] = sum over units [first[c], first[c] + count[c]) for
+// q < kPartials, then the shifts ref[2 c], ref[2 c + 1] the sums were taken
+// with; ref is then moved to the means of dP and P found (when finite).
+hipError_t launch_reduce_partials(const double* partial, const int32_t* first, const int32_t* count,
+                                  const CavityDesc* desc, int n_cav, double* ref, double* out, hipStream_t s);
 
 // u, v, P (FP64 or FP32 by dtype) of one cavity, [j][i] packed.
 hipError_t launch_fields(int prec, const void* f, const CavityDesc* desc, int cav_index, const CavityDesc& hd,

@@ -27,12 +27,17 @@ __global__ __launch_bounds__(kNodeBlock) void k_init(void* fv, void* lv, const C
     static_cast<typename S::L*>(lv)[c.l_off + id] = T(c.lam0);
 }
 
-// out[c][q] = sum of partial[u][q] over the units of cavity c, in a fixed order.
-__global__ __launch_bounds__(256) void k_reduce(const double* partial, const int32_t* first, const int32_t* count, double* out)
+// out[c][q] = sum of partial[u][q] over the units of cavity c, in a fixed
+// order, then the shifts the sums were taken with; the shifts move to the
+// means of dP and P just found, for the next evaluation.
+__global__ __launch_bounds__(256) void k_reduce(const double* partial, const int32_t* first, const int32_t* count,
+                                                const CavityDesc* desc, double* ref, double* out)
 {
     __shared__ double sh[kPartials][256];
     const int c = blockIdx.x;
-    double v[kPartials] = {0, 0, 0, 0, 0, 0, 0};
+    double v[kPartials];
+#pragma unroll
+    for (int q = 0; q < kPartials; ++q) v[q] = 0.0;
     for (int u = threadIdx.x; u < count[c]; u += 256)
 #pragma unroll
         for (int q = 0; q < kPartials; ++q) v[q] += partial[(int64_t)(first[c] + u) * kPartials + q];
@@ -45,7 +50,20 @@ __global__ __launch_bounds__(256) void k_reduce(const double* partial, const int
             for (int q = 0; q < kPartials; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x < kPartials) out[(int64_t)c * kPartials + threadIdx.x] = sh[threadIdx.x][0];
+    double* o = out + (int64_t)c * kResult;
+    if (threadIdx.x < kPartials) o[threadIdx.x] = sh[threadIdx.x][0];
+    if (threadIdx.x == 0) {
+        const double rd = ref[2 * c], rp = ref[2 * c + 1];
+        o[kPartials] = rd;
+        o[kPartials + 1] = rp;
+        if (count[c] == 0) return;   // a stopped cavity keeps its shifts
+        const double nn = (double)desc[c].nx * (double)desc[c].ny;
+        const double md = rd + sh[4][0] / nn, mp = rp + sh[5][0] / nn;
+        if (isfinite(md) && isfinite(mp)) {
+            ref[2 * c] = md;
+            ref[2 * c + 1] = mp;
+        }
+    }
 }
 
 template <int PREC, typename O>
@@ -237,11 +255,11 @@ hipError_t launch_seed_bump(uint32_t* ctr, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_partials(const double* partial, const int32_t* first, const int32_t* count, int n_cav, double* out,
-                                  hipStream_t s)
+hipError_t launch_reduce_partials(const double* partial, const int32_t* first, const int32_t* count,
+                                  const CavityDesc* desc, int n_cav, double* ref, double* out, hipStream_t s)
 {
     if (n_cav <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce, dim3(n_cav), dim3(256), 0, s, partial, first, count, out);
+    hipLaunchKernelGGL(k_reduce, dim3(n_cav), dim3(256), 0, s, partial, first, count, desc, ref, out);
     return hipGetLastError();
 }
 

@@ -269,19 +269,25 @@ __device__ __forceinline__ void half_step(const T (&fb)[9], V lam, V dt, T (&out
     for (int k = 0; k < 9; ++k) out[k] = fb[k] + b * (e[k] - fb[k]);
 }
 
+// Eq. (2.19) sums of one node (the layout of kPartials); ref holds the
+// cavity's shifts r_d, r_p.
 template <typename T>
-__device__ __forceinline__ void residual_add(const T (&gn)[9], const T (&old)[3], double (&acc)[kPartials])
+__device__ __forceinline__ void residual_add(const T (&gn)[9], const T (&old)[3], const double (&ref)[2],
+                                             double (&acc)[kPartials])
 {
     T P, ux, uy;
     moments(gn, P, ux, uy);
     const double du = (double)ux - (double)old[1], dv = (double)uy - (double)old[2], dp = (double)P - (double)old[0];
+    const double sd = dp - ref[0], sp = (double)P - ref[1];
     acc[0] += du * du + dv * dv;
     acc[1] += (double)ux * ux + (double)uy * uy;
     acc[2] += dp * dp;
     acc[3] += (double)P * P;
-    acc[4] += dp;
-    acc[5] += (double)P;
+    acc[4] += sd;
+    acc[5] += sp;
     acc[6] += (isfinite((double)ux) && isfinite((double)uy) && isfinite((double)P)) ? 0.0 : 1.0;
+    acc[7] += sd * sd;
+    acc[8] += sp * sp;
 }
 
 // One work item.  Register ring slot of row t - d at unrolled phase R:
@@ -303,6 +309,7 @@ struct March {
     const CavityDesc& c;
     WaveLds<T, S::kExactFinal ? 9 : 0>& sh;
     double (&acc)[kPartials];
+    double ref[2];         // shifts of the residual sums (RES)
 
     int lane, nx, ny, i, ic, j0, j1, qlo, qhi, t_begin, t_last;
     bool out_col, walls_b, walls_c;
@@ -334,7 +341,7 @@ struct March {
     __device__ __forceinline__ March(const StepArgs& a_, const StripItem& it_, const CavityDesc& c_,
                                      WaveLds<T, S::kExactFinal ? 9 : 0>& sh_,
                                      double (&acc_)[kPartials])
-        : a(a_), it(it_), c(c_), sh(sh_), acc(acc_), pl(c_),
+        : a(a_), it(it_), c(c_), sh(sh_), acc(acc_), ref{0.0, 0.0}, pl(c_),
           xl(threadIdx.x, it_.i0 - kHaloCols + (int)threadIdx.x, c_.nx,
              geo_of<T>(a_)[c_.geo_off + c_.ny + min(max(it_.i0 - kHaloCols + (int)threadIdx.x, 0), c_.nx - 1)])
     {
@@ -366,6 +373,10 @@ struct March {
         rf_out = buffer_of(static_cast<F*>(a.f_out) + c.f_off, 9u * fpb);
         rl_in = buffer_of(static_cast<const L*>(a.l_in) + c.l_off, (uint32_t)c.plane * (uint32_t)sizeof(L));
         rl_out = buffer_of(static_cast<L*>(a.l_out) + c.l_off, (uint32_t)c.plane * (uint32_t)sizeof(L));
+        if (RES) {
+            ref[0] = a.res_ref[2 * it.cav];
+            ref[1] = a.res_ref[2 * it.cav + 1];
+        }
         skey = S::kStochastic ? step_key(a.seed_ctr[0], a.step) : 0u;
         ckey = S::kStochastic ? cavity_key(it.cav) : 0u;
 #pragma unroll
@@ -690,7 +701,7 @@ struct March {
             if (RES && out_col) {
                 T old[3];
                 old_moments(p, old);
-                residual_add(gn, old, acc);
+                residual_add(gn, old, ref, acc);
             }
             if (p == 1 && j0 == 0) {   // bottom wall row from row 1
                 T src[9], g0[9];
@@ -701,7 +712,7 @@ struct March {
                     if (RES) {
                         T old[3];
                         old_moments(0, old);
-                        residual_add(g0, old, acc);
+                        residual_add(g0, old, ref, acc);
                     }
                 }
             }
@@ -714,7 +725,7 @@ struct March {
                     if (RES) {
                         T old[3];
                         old_moments(ny - 1, old);
-                        residual_add(gl, old, acc);
+                        residual_add(gl, old, ref, acc);
                     }
                 }
             }
@@ -790,7 +801,9 @@ __global__ __launch_bounds__(kWaveLanes, Tuning<PREC>::kWaves) void k_fused(Step
     if (it.unit < 0) return;   // padding of a per-XCD queue
     const CavityDesc c = a.desc[it.cav];
     __shared__ WaveLds<typename Storage<PREC>::T, Storage<PREC>::kExactFinal ? 9 : 0> sh;
-    double acc[kPartials] = {0, 0, 0, 0, 0, 0, 0};
+    double acc[kPartials];
+#pragma unroll
+    for (int q = 0; q < kPartials; ++q) acc[q] = 0.0;
     // waves that hold column 1 or nx-2 take the first-order one-sided points (Eq. 2.7 at walls)
     if (IFD_FUSED_ONE_PATH || it.i0 <= 5 || it.i1 >= c.nx - 5)
         March<PREC, RES, true, IMPL>(a, it, c, sh, acc);

@@ -245,7 +245,9 @@ __global__ __launch_bounds__(kNodeBlock) void k_residual(StepArgs a, const NodeB
     __shared__ double sh[kPartials][kNodeBlock];
     CavityDesc c;
     NodeRef r;
-    double v[kPartials] = {0, 0, 0, 0, 0, 0, 0};
+    double v[kPartials];
+#pragma unroll
+    for (int q = 0; q < kPartials; ++q) v[q] = 0.0;
     if (locate(blocks, b0 + blockIdx.x, a.desc, c, r)) {
         const auto* fi = static_cast<const typename S::F*>(a.f_in);
         const auto* fo = static_cast<const typename S::F*>(a.f_out);
@@ -262,9 +264,12 @@ __global__ __launch_bounds__(kNodeBlock) void k_residual(StepArgs a, const NodeB
         v[1] = (double)u1 * u1 + (double)v1 * v1;
         v[2] = dp * dp;
         v[3] = (double)P1 * P1;
-        v[4] = dp;
-        v[5] = (double)P1;
+        const double sd = dp - a.res_ref[2 * c.index], sp = (double)P1 - a.res_ref[2 * c.index + 1];
+        v[4] = sd;
+        v[5] = sp;
         v[6] = (isfinite((double)u1) && isfinite((double)v1) && isfinite((double)P1)) ? 0.0 : 1.0;
+        v[7] = sd * sd;
+        v[8] = sp * sp;
     }
 #pragma unroll
     for (int q = 0; q < kPartials; ++q) sh[q][threadIdx.x] = v[q];

@@ -56,7 +56,7 @@ class ifdlbm_options(ctypes.Structure):
                 ("rho0", ctypes.c_double), ("gamma_min", ctypes.c_double), ("residual_every", ctypes.c_int32),
                 ("kernel", ctypes.c_int32), ("batched", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
                 ("dt_rule", ctypes.c_int32), ("segment_rows", ctypes.c_int32), ("lambda_mode", ctypes.c_int32),
-                ("hip_stream", ctypes.c_void_p)]
+                ("pressure_residual", ctypes.c_int32), ("hip_stream", ctypes.c_void_p)]
 
 
 class ifdlbm_info_t(ctypes.Structure):
@@ -73,6 +73,8 @@ class ifdlbm_regime_t(ctypes.Structure):
 
 IFDLBM_LAMBDA_LAGGED = 0
 IFDLBM_LAMBDA_IMPLICIT = 1
+IFDLBM_EP_MEAN_REMOVED = 0
+IFDLBM_EP_PRINTED = 1
 
 IFDLBM_REGIME_STEADY = 0
 IFDLBM_REGIME_PERIODIC = 1
@@ -99,6 +101,7 @@ def lib():
         L.ifdlbm_sync.argtypes = [_H]
         L.ifdlbm_run_to_steady.argtypes = [_H, ctypes.c_double, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), _D, _D]
         L.ifdlbm_get_residuals.argtypes = [_H, _D, _D]
+        L.ifdlbm_get_pressure_residuals.argtypes = [_H, _D, _D]
         L.ifdlbm_get_fields.argtypes = [_H, ctypes.c_int32, _D, _D, _D]
         L.ifdlbm_get_fields_device.argtypes = [_H, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                ctypes.c_int32]
@@ -231,6 +234,14 @@ def ifdlbm_get_residuals(h: Handle):
     return ru, rp
 
 
+def ifdlbm_get_pressure_residuals(h: Handle):
+    """(E(P) as printed, E(P) with the spatial mean of P removed) of Eq. (2.19), per cavity."""
+    n = len(h.cavities)
+    printed, mean_removed = np.zeros(n), np.zeros(n)
+    _check(lib().ifdlbm_get_pressure_residuals(h.ptr, _dptr(printed), _dptr(mean_removed)))
+    return printed, mean_removed
+
+
 def ifdlbm_get_fields(h: Handle, cav: int):
     shp = h.shape(cav)
     u, v, p = np.zeros(shp), np.zeros(shp), np.zeros(shp)
@@ -239,7 +250,8 @@ def ifdlbm_get_fields(h: Handle, cav: int):
 
 
 def ifdlbm_get_fields_device(h: Handle, cav: int, u, v, p) -> None:
-    """u, v, p: contiguous torch tensors of n_eta * n_xi float64 or float32 on the device."""
+    """u, v, p: contiguous torch tensors of n_eta * n_xi float64 or float32 on the device.  With a caller
+    stream in the options the copy is enqueued there; with the handle's own stream the call waits for it."""
     dt = {8: 0, 4: 1}[u.element_size()]
     for t in (u, v, p):
         assert t.is_contiguous() and t.numel() == h.shape(cav)[0] * h.shape(cav)[1] and t.element_size() == u.element_size()

@@ -2,7 +2,7 @@
 
 python -m paper_2306_07603_amd.studies <name> [--out FILE] [options]
 
-  regime     Section 6.3: the flow regime (steady / periodic / quasi-periodic /
+  regime     Section 6.2: the flow regime (steady / periodic / quasi-periodic /
              aperiodic) of the cavities whose regime the paper reports, from the
              centre velocity and the kinetic energy of Eq. (5.1) recorded on the
              device, classified by the library's spectral classifier.
@@ -31,7 +31,7 @@ import numpy as np
 
 from . import ifdlbm as M
 
-# (theta, n, Re, regime the paper reports) -- Section 6.3, 256 x 256 grids
+# (theta, n, Re, regime the paper reports) -- Section 6.2, 256 x 256 grids
 PAPER_REGIMES = [
     (60.0, 1.5, 3000.0, "steady"), (60.0, 1.5, 4000.0, "periodic"), (60.0, 1.5, 5000.0, "periodic"),
     (60.0, 1.0, 2000.0, "steady"), (60.0, 1.0, 2500.0, "periodic"), (60.0, 1.0, 3000.0, "quasi-periodic"),

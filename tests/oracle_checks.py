@@ -175,6 +175,26 @@ def check_relaxation_time_power_law():
         assert abs(got - 1e-3 * (1e-6) ** ((n - 1) / 2) / cs2) < 1e-12 * got
 
 
+def check_initial_lambda():
+    """Step (1), reading R9: the initial relaxation time is the power-law value
+    at the cavity's characteristic strain rate U / L.  Built here from the
+    paper's definitions one at a time: K from Re = U^(2-n) L^n / K
+    (Eq. 2.15.1, L = 1), mu = K gamma^(n-1) at gamma = U / L (Eq. 1.4),
+    lambda = mu / c_s^2 (Eq. 2.14) with c_s^2 from the lattice isotropy."""
+    _, _, _, _, cs2 = O.lattice()
+    L = 1.0
+    for re, n, U, th in ((100.0, 0.8, 0.1, 60.0), (2500.0, 1.5, 0.1, 45.0), (40.0, 0.5, -0.05, 90.0),
+                         (400.0, 1.0, 0.2, 75.0)):
+        p = O.Params(nx=9, ny=7, re=re, n=n, u_lid=U, theta_deg=th)
+        K = abs(U) ** (2.0 - n) * L ** n / re
+        gamma = abs(U) / L
+        mu = K * gamma ** (n - 1.0)
+        want = mu / cs2
+        _, Lam = O.init(p)
+        assert np.all(np.abs(Lam - want) <= 1e-14 * want), (re, n, U, Lam.ravel()[0], want)
+        assert abs(O.derive(p)["K"] - K) <= 1e-15 * K
+
+
 def check_implicit_lambda():
     """Implicit Step (2) (reading R20): (a) for a node whose f carries the
     non-equilibrium part of a strain rate S at the power-law lambda of S
@@ -563,6 +583,7 @@ ALL_CHECKS = [
     check_conversions_follow_definitions,
     check_collision_invariants,
     check_relaxation_time_power_law,
+    check_initial_lambda,
     check_implicit_lambda,
     check_implicit_steady_state_equals_lagged,
     check_geometry_matches_paper,

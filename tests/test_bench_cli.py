@@ -49,3 +49,26 @@ def test_counter_record_covers_the_autotuner_choices():
         for seg in range(32, 81, 8):
             for what in ("bytes", "valu_insts"):
                 assert float(rec["%s_per_launch_%s_seg%d" % (what, prec, seg)]) > 0, (what, prec, seg)
+
+
+def test_timed_schedule_and_what_it_runs():
+    """The timed region of the default run is whole graph replays each with one residual step; with fewer
+    timed steps than a graph holds, the graph and the residual interval shrink to the timed count and the
+    warm-up rounds up to whole graphs."""
+    sys.path.insert(0, ROOT)
+    import bench
+    assert bench.timed_schedule(20000, 100, 100, 100) == (100, 100, 100)
+    ex = bench.executed(100, 20000, 100, 100)
+    assert (ex["graph_replays"], ex["eager_steps"], ex["residual_steps"]) == (200, 0, 200)
+    G, R, W = bench.timed_schedule(20, 5, 100, 100)
+    assert (G, R, W) == (20, 20, 20)
+    ex = bench.executed(W, 20, G, R)
+    assert (ex["graph_replays"], ex["eager_steps"], ex["residual_steps"]) == (1, 0, 1)
+    assert bench.timed_schedule(7, 5, 100, 100) == (6, 6, 6)
+    # without the adjustment, 20 steps from step 5 run eagerly with no residual step
+    ex = bench.executed(5, 20, 100, 100)
+    assert (ex["graph_replays"], ex["eager_steps"], ex["residual_steps"]) == (0, 20, 0)
+    # a replay starts only at a multiple of the graph size: 70 eager steps, one replay, 80 eager steps
+    ex = bench.executed(30, 250, 100, 50)
+    assert (ex["graph_replays"], ex["eager_steps"], ex["residual_steps"]) == (1, 150, 5)
+    assert "1 replays of a 100-step HIP graph" in bench.describe(ex) and "150 eager steps" in bench.describe(ex)

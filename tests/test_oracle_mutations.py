@@ -51,6 +51,10 @@ MUTATIONS = [
      [C.check_implicit_lambda]),
     ("viscosity_from_consistency", "return mu / CS2;", "return mu * CS2;",
      [C.check_relaxation_time_power_law, C.check_taylor_green_decay]),
+    ("initial_lambda_drops_cs2", "d->lam0 = U / (p->re * CS2);", "d->lam0 = U / p->re;",
+     [C.check_initial_lambda]),
+    ("initial_lambda_newtonian_only", "d->lam0 = U / (p->re * CS2);", "d->lam0 = pow(U, 2.0 - p->n) / (p->re * CS2);",
+     [C.check_initial_lambda]),
 ]
 
 
