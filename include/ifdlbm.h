@@ -286,6 +286,10 @@ int ifdlbm_classify(const double* x, int64_t n, double dt_sample, double steady_
 /* Frees the handle and its device memory; NULL-safe. */
 void ifdlbm_destroy(ifdlbm_t* h);
 
+/* SHA-256 (hex) of the sources the library was built from, so that a binding can refuse a library that no
+   longer matches its sources.  Static text. */
+const char* ifdlbm_build_digest(void);
+
 /* Static text for an IFDLBM_E* code, and the calling thread's last error message. */
 const char* ifdlbm_strerror(int code);
 const char* ifdlbm_last_error(void);

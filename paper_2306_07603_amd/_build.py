@@ -23,6 +23,24 @@ FLAGS = [
 ]
 
 
+def source_files():
+    """Every file the library is built from: the sources, the headers beside them and the C-ABI header."""
+    heads = sorted(f for f in os.listdir(CSRC) if f.endswith(".h"))
+    return [os.path.join(CSRC, f) for f in SOURCES + heads] + [os.path.join(INCLUDE, "ifdlbm.h")]
+
+
+def source_digest() -> str:
+    """SHA-256 of the library's sources (names and contents), compiled into the library as
+    ifdlbm_build_digest() so that the binding can refuse a library built from other sources."""
+    import hashlib
+    h = hashlib.sha256()
+    for path in source_files():
+        with open(path, "rb") as f:
+            data = f.read()
+        h.update(os.path.basename(path).encode() + b"\0" + str(len(data)).encode() + b"\0" + data)
+    return h.hexdigest()
+
+
 def _compile(src: str, obj: str, extra) -> None:
     cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -37,8 +55,9 @@ def build(extra=(), jobs: int = 4, out: str = LIB, objdir: str = "") -> str:
     objdir = objdir or os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
     objs = [os.path.join(objdir, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+    extra = list(extra) + ['-DIFD_SOURCE_DIGEST="%s"' % source_digest()]
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        list(ex.map(lambda so: _compile(so[0], so[1], list(extra)), zip(SOURCES, objs)))
+        list(ex.map(lambda so: _compile(so[0], so[1], extra), zip(SOURCES, objs)))
     tmp = out + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -1233,6 +1233,11 @@ const char* ifdlbm_strerror(int code)
 
 const char* ifdlbm_last_error(void) { return g_last_error.c_str(); }
 
+#ifndef IFD_SOURCE_DIGEST
+#error "IFD_SOURCE_DIGEST: build the library with paper_2306_07603_amd/_build.py"
+#endif
+const char* ifdlbm_build_digest(void) { return IFD_SOURCE_DIGEST; }
+
 
 // C entry points: no C++ exception crosses the ABI.
 int ifdlbm_create(const ifdlbm_cavity* cav, int32_t n_cav, const ifdlbm_options* opt, ifdlbm_t** out)

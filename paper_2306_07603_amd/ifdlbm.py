@@ -20,8 +20,7 @@ except ImportError:
     torch = None
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-# IFDLBM_LIB may name another build of the library (for A/B timing of build variants)
-LIB_PATH = os.environ.get("IFDLBM_LIB") or os.path.join(_PKG, "libifdlbm.so")
+LIB_PATH = os.path.join(_PKG, "libifdlbm.so")
 
 IFDLBM_OK = 0
 IFDLBM_EINVAL = -1
@@ -94,6 +93,7 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError("libifdlbm.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
         L = ctypes.CDLL(LIB_PATH)
+        verify_build(L)
         L.ifdlbm_default_options.argtypes = [ctypes.POINTER(ifdlbm_options)]
         L.ifdlbm_create.argtypes = [ctypes.POINTER(ifdlbm_cavity), ctypes.c_int32, ctypes.POINTER(ifdlbm_options),
                                     ctypes.POINTER(_H)]
@@ -129,6 +129,17 @@ def lib():
         L.ifdlbm_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
+
+
+def verify_build(L) -> None:
+    """Refuse a library built from other sources than the ones beside it (a stale build)."""
+    from . import _build
+    L.ifdlbm_build_digest.argtypes = []
+    L.ifdlbm_build_digest.restype = ctypes.c_char_p
+    built, here = L.ifdlbm_build_digest().decode(), _build.source_digest()
+    if built != here:
+        raise ImportError("%s was built from other sources (digest %s...) than those in %s (digest %s...); "
+                          "rebuild with __graft_entry__.build()" % (LIB_PATH, built[:12], _build.CSRC, here[:12]))
 
 
 def _strerror(code: int) -> str:
@@ -362,3 +373,8 @@ def ifdlbm_strerror(code: int) -> str:
 
 def ifdlbm_last_error() -> str:
     return lib().ifdlbm_last_error().decode()
+
+
+def ifdlbm_build_digest() -> str:
+    """SHA-256 of the sources the loaded library was built from."""
+    return lib().ifdlbm_build_digest().decode()

@@ -114,3 +114,14 @@ def test_gradient_calls_reject_bad_arguments():
 def test_autotune_rejects_bad_arguments():
     L = M.lib()
     assert L.ifdlbm_autotune(None, 5, None, None) == M.IFDLBM_EINVAL
+
+
+def test_stale_library_is_refused(monkeypatch):
+    """The library carries the digest of the sources it was built from; the binding refuses a library whose
+    digest differs from that of the sources beside it."""
+    from paper_2306_07603_amd import _build
+    L = M.ifdlbm.lib()
+    assert M.ifdlbm_build_digest() == _build.source_digest()
+    monkeypatch.setattr(_build, "source_digest", lambda: "0" * 64)
+    with pytest.raises(ImportError, match="rebuild"):
+        M.ifdlbm.verify_build(L)
