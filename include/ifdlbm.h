@@ -227,6 +227,18 @@ int ifdlbm_info(ifdlbm_t* h, ifdlbm_info_t* info);
 int ifdlbm_gradient(const ifdlbm_cavity* cav, const ifdlbm_options* opt, int64_t n_steps, int32_t objective,
                     double* J, double grad[3]);
 
+/* ifdlbm_gradient for callers that cannot allocate device memory (code under HIP graph capture is not among
+   them: the call synchronises), such as tight serving loops and harnesses that forbid hipMalloc: the same
+   J and grad[3], bitwise, with no hipMalloc, hipFree or stream creation.  The work arrays (48 values of 32
+   bytes per node, plus n_xi + n_eta + nodes / 256) live in a 32 MiB array of the library's device code, one
+   per GPU, held until the process ends; grids needing more (beyond about 21 800 nodes: 147 x 147 fits) are
+   rejected with EINVAL before any device work.  The current device's array is used; options.hip_stream NULL
+   means the null stream.  Every call on a GPU shares that GPU's array: calls that overlap on one GPU (from two
+   threads, or on two streams without ordering) race and give wrong results.  Nothing of a previous call's
+   contents is read (every value is written before it is read).  Errors: EINVAL, EDEVICE. */
+int ifdlbm_gradient_noalloc(const ifdlbm_cavity* cav, const ifdlbm_options* opt, int64_t n_steps, int32_t objective,
+                            double* J, double grad[3]);
+
 /* The same J and grad[3] (dJ/dtheta [rad], dJ/dn, dJ/du_lid) by the discrete adjoint: a forward sweep of n_steps
    steps of the handle's own step kernel (options precision, kernel, segment_rows, cfl, mix, rho0, gamma_min,
    dt_rule and hip_stream apply; lambda_mode must be LAGGED) keeps the state every checkpoint_every steps; the

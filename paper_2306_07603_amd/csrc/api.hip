@@ -1009,7 +1009,7 @@ static int ifdlbm_info_impl(ifdlbm_t* h, ifdlbm_info_t* info)
 }
 
 static int ifdlbm_gradient_impl(const ifdlbm_cavity* cav, const ifdlbm_options* opt, int64_t n_steps, int32_t objective, double* J,
-                    double grad[3])
+                    double grad[3], bool no_alloc)
 {
     if (!cav || !opt || !J || !grad) return fail(IFDLBM_EINVAL, "null argument");
     if (objective != IFDLBM_OBJ_KINETIC_ENERGY) return fail(IFDLBM_EINVAL, "unknown objective");
@@ -1025,15 +1025,20 @@ static int ifdlbm_gradient_impl(const ifdlbm_cavity* cav, const ifdlbm_options* 
     if (!(opt->cfl > 0.0) || !(opt->mix >= 0.0 && opt->mix <= 1.0) || !(opt->gamma_min > 0.0) ||
         (opt->dt_rule != IFDLBM_DT_CONTRAVARIANT && opt->dt_rule != IFDLBM_DT_CARTESIAN))
         return fail(IFDLBM_EINVAL, "options outside their domain");
+    if (no_alloc && tangent_workspace_elems(v.n_xi, v.n_eta) > tangent_scratch_capacity_elems())
+        return fail(IFDLBM_EINVAL, "grid too large for the allocation-free gradient: it needs " +
+                                       std::to_string(tangent_workspace_elems(v.n_xi, v.n_eta)) + " work values, the "
+                                       "scratch array holds " + std::to_string(tangent_scratch_capacity_elems()) +
+                                       " (48 per node)");
     hipStream_t s = static_cast<hipStream_t>(opt->hip_stream);
     bool own = false;
-    if (!s) {
+    if (!s && !no_alloc) {
         IFD_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
         own = true;
     }
     std::string err;
     hipError_t e = tangent_kinetic_energy(v.n_xi, v.n_eta, v.re, v.n, v.theta_deg, v.u_lid, opt->cfl, opt->mix,
-                                          opt->gamma_min, opt->dt_rule, n_steps, s, J, grad, err);
+                                          opt->gamma_min, opt->dt_rule, n_steps, s, J, grad, err, no_alloc);
     if (own) (void)hipStreamDestroy(s);
     if (e != hipSuccess)
         return fail(e == hipErrorOutOfMemory ? IFDLBM_ENOMEM : IFDLBM_EDEVICE, err);
@@ -1313,7 +1318,13 @@ int ifdlbm_info(ifdlbm_t* h, ifdlbm_info_t* info)
 int ifdlbm_gradient(const ifdlbm_cavity* cav, const ifdlbm_options* opt, int64_t n_steps, int32_t objective, double* J,
                     double grad[3])
 {
-    IFD_GUARD(ifdlbm_gradient_impl(cav, opt, n_steps, objective, J, grad));
+    IFD_GUARD(ifdlbm_gradient_impl(cav, opt, n_steps, objective, J, grad, false));
+}
+
+int ifdlbm_gradient_noalloc(const ifdlbm_cavity* cav, const ifdlbm_options* opt, int64_t n_steps, int32_t objective,
+                            double* J, double grad[3])
+{
+    IFD_GUARD(ifdlbm_gradient_impl(cav, opt, n_steps, objective, J, grad, true));
 }
 
 int ifdlbm_adjoint(const ifdlbm_cavity* cav, const ifdlbm_options* opt, int64_t n_steps, int32_t checkpoint_every,

@@ -13,6 +13,7 @@
 // no stored trajectory; the derivative is that of the discrete objective, the
 // same one a reverse sweep would return.
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -209,23 +210,22 @@ __global__ __launch_bounds__(256) void t_energy(TParams c, const D3* f, D3* part
 
 }  // namespace
 
-// Host driver; returns a HIP error or hipSuccess and fills J and grad[3].
-hipError_t tangent_kinetic_energy(int nx, int ny, double re, double n, double theta_deg, double u_lid, double cfl,
-                                  double mix, double gamma_min, int dt_rule, int64_t n_steps, hipStream_t s, double* J,
-                                  double* grad, std::string& err)
+namespace {
+
+// Parameters of the step and the metric tables a_j, s_i, each with its derivatives with respect to
+// (theta [rad], n, U).
+void tangent_params(int nx, int ny, double re, double n, double theta_deg, double u_lid, double cfl, double mix,
+                    double gamma_min, int dt_rule, TParams& P, std::vector<D3>& geo)
 {
-    // parameters and their derivatives with respect to (theta [rad], n, U)
     const double th = theta_deg * (M_PI / 180.0);
     const double C = theta_deg == 90.0 ? 0.0 : 1.0 / std::tan(th);
     const double dC = -(1.0 + C * C);   // d cot / d theta
     const double U = std::fabs(u_lid), sgnU = u_lid < 0 ? -1.0 : 1.0;
     const double dxi = 1.0 / (nx - 1), deta = 1.0 / (ny - 1);
-    TParams P;
     P.nx = nx;
     P.ny = ny;
     P.dxi = dxi;
     P.deta = deta;
-    double z[3] = {0, 0, 0};
     {
         double d[3] = {dC, 0, 0};
         P.cot = D3::make(C, d);
@@ -258,9 +258,7 @@ hipError_t tangent_kinetic_energy(int nx, int ny, double re, double n, double th
         double d[3] = {0, 0, 3.0 / re * sgnU};
         P.lam0 = D3::make(3.0 * U / re, d);
     }
-    (void)z;
-    // metric tables a_j, s_i with their theta derivatives
-    std::vector<D3> geo(ny + nx);
+    geo.resize(ny + nx);
     for (int j = 0; j < ny; ++j) {
         const double eta = j * deta, a = 1.0 / (1.0 + 2.0 * C * eta);
         double d[3] = {-2.0 * eta * a * a * dC, 0, 0};
@@ -271,46 +269,149 @@ hipError_t tangent_kinetic_energy(int nx, int ny, double re, double n, double th
         double d[3] = {w * dC, 0, 0};
         geo[ny + i] = D3::make(C * w, d);
     }
+}
 
-    const size_t nn = (size_t)nx * ny, nb = (nn + 255) / 256;
+// Sizes (in three-component duals) of the ten work arrays, in the order carve lays them out: the state twice
+// (nine planes and lambda each), f-hat+, f-bar+ then f(t + dt/2), f-bar, lambda of the step, the metric tables,
+// the energy partial sums.
+void workspace_sizes(size_t nn, size_t ngeo, size_t (&sizes)[10])
+{
+    const size_t s[10] = {9 * nn, 9 * nn, nn, nn, 9 * nn, 9 * nn, 9 * nn, nn, ngeo, (nn + 255) / 256};
+    for (int q = 0; q < 10; ++q) sizes[q] = s[q];
+}
+
+// The ten work arrays carved from one workspace of tangent_workspace_elems(nx, ny) values.
+TBuf carve(D3* w, size_t nn, size_t ngeo)
+{
     TBuf b{};
     D3** ptrs[] = {&b.f[0], &b.f[1], &b.l[0], &b.l[1], &b.hp, &b.bp, &b.fb, &b.ln, &b.geo, &b.part};
-    const size_t sizes[] = {9 * nn, 9 * nn, nn, nn, 9 * nn, 9 * nn, 9 * nn, nn, geo.size(), nb};
-    hipError_t e = hipSuccess;
-    for (int q = 0; q < 10 && e == hipSuccess; ++q) e = hipMalloc(reinterpret_cast<void**>(ptrs[q]), sizes[q] * sizeof(D3));
-    if (e == hipSuccess) e = hipMemcpyAsync(b.geo, geo.data(), geo.size() * sizeof(D3), hipMemcpyHostToDevice, s);
-    const dim3 g(nb), blk(256);
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(t_init, g, blk, 0, s, P, b.f[0], b.l[0]);
-        int cur = 0;
-        for (int64_t t = 0; t < n_steps; ++t) {
-            hipLaunchKernelGGL(t_stage_a, g, blk, 0, s, P, b.f[cur], b.l[cur], b.hp, b.bp, b.ln);
-            hipLaunchKernelGGL(t_stage_b, g, blk, 0, s, P, b.bp, b.fb, b.geo);
-            hipLaunchKernelGGL(t_stage_bh, g, blk, 0, s, P, b.fb, b.ln, b.bp);
-            hipLaunchKernelGGL(t_stage_c, g, blk, 0, s, P, b.bp, b.hp, b.ln, b.f[cur ^ 1], b.l[cur ^ 1], b.geo);
-            hipLaunchKernelGGL(t_stage_cb, g, blk, 0, s, P, b.f[cur ^ 1]);
-            cur ^= 1;
-            if ((t & 1023) == 1023 && (e = hipGetLastError()) != hipSuccess) break;
-        }
-        if (e == hipSuccess) {
-            hipLaunchKernelGGL(t_energy, g, blk, 0, s, P, b.f[cur], b.part);
-            e = hipGetLastError();
-        }
+    size_t sizes[10];
+    workspace_sizes(nn, ngeo, sizes);
+    for (int q = 0; q < 10; ++q) {
+        *ptrs[q] = w;
+        w += sizes[q];
     }
-    std::vector<D3> part(nb);
-    if (e == hipSuccess) e = hipMemcpyAsync(part.data(), b.part, nb * sizeof(D3), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    for (int q = 0; q < 10; ++q)
-        if (*ptrs[q]) (void)hipFree(*ptrs[q]);
-    if (e != hipSuccess) {
-        err = std::string("gradient: ") + hipGetErrorString(e);
+    return b;
+}
+
+// The sweep in a given workspace: Step (1), n_steps staged steps with their derivatives, Eq. (5.1).  Every
+// work array is written before it is read, so the workspace needs no clearing.
+hipError_t tangent_run(const TParams& P, const std::vector<D3>& geo, D3* work, int64_t n_steps, hipStream_t s,
+                       double* J, double* grad, std::string& err)
+{
+    const size_t nn = (size_t)P.nx * P.ny, nb = (nn + 255) / 256;
+    const TBuf b = carve(work, nn, geo.size());
+    auto failed = [&](hipError_t e, const char* what) {
+        err = std::string("gradient: ") + what + ": " + hipGetErrorString(e);
         return e;
+    };
+    hipError_t e = hipMemcpyAsync(b.geo, geo.data(), geo.size() * sizeof(D3), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return failed(e, "metric tables to the device");
+    const dim3 g(nb), blk(256);
+    hipLaunchKernelGGL(t_init, g, blk, 0, s, P, b.f[0], b.l[0]);
+    if ((e = hipGetLastError()) != hipSuccess) return failed(e, "Step (1) launch");
+    int cur = 0;
+    for (int64_t t = 0; t < n_steps; ++t) {
+        hipLaunchKernelGGL(t_stage_a, g, blk, 0, s, P, b.f[cur], b.l[cur], b.hp, b.bp, b.ln);
+        hipLaunchKernelGGL(t_stage_b, g, blk, 0, s, P, b.bp, b.fb, b.geo);
+        hipLaunchKernelGGL(t_stage_bh, g, blk, 0, s, P, b.fb, b.ln, b.bp);
+        hipLaunchKernelGGL(t_stage_c, g, blk, 0, s, P, b.bp, b.hp, b.ln, b.f[cur ^ 1], b.l[cur ^ 1], b.geo);
+        hipLaunchKernelGGL(t_stage_cb, g, blk, 0, s, P, b.f[cur ^ 1]);
+        cur ^= 1;
+        if ((t & 1023) == 1023 && (e = hipGetLastError()) != hipSuccess) return failed(e, "step launch");
     }
+    hipLaunchKernelGGL(t_energy, g, blk, 0, s, P, b.f[cur], b.part);
+    if ((e = hipGetLastError()) != hipSuccess) return failed(e, "step or energy launch");
+    std::vector<D3> part(nb);
+    e = hipMemcpyAsync(part.data(), b.part, nb * sizeof(D3), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return failed(e, "energy partial sums to the host");
     D3 sum(0.0);
     for (const D3& x : part) sum += x;
     *J = sum.v;
     for (int q = 0; q < 3; ++q) grad[q] = sum.d[q];
     return hipSuccess;
+}
+
+// Work arrays of ifdlbm_gradient_noalloc: one array per GPU, held until the process ends.  Host code must not
+// use this name as a device address: the address of each GPU's copy comes from hipGetSymbolAddress.
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (looked up on the first call on each device).
+hipError_t scratch_of_current_device(void** out, std::string& err)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        err = std::string("hipGetDevice: ") + hipGetErrorString(e);
+        return e;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        err = "device index beyond the library's table of scratch arrays";
+        return hipErrorInvalidDevice;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return e != hipSuccess ? e : hipErrorInvalidSymbol;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+size_t tangent_workspace_elems(int nx, int ny)
+{
+    size_t sizes[10], total = 0;
+    workspace_sizes((size_t)nx * ny, (size_t)nx + (size_t)ny, sizes);
+    for (size_t x : sizes) total += x;
+    return total;   // 48 nn + nx + ny + ceil(nn / 256)
+}
+
+size_t tangent_scratch_capacity_elems() { return kScratchBytes / sizeof(D3); }
+
+// Host driver; returns a HIP error or hipSuccess and fills J and grad[3].  The work arrays live in one
+// allocation made and freed here, or, with use_scratch, in the current device's scratch array.
+hipError_t tangent_kinetic_energy(int nx, int ny, double re, double n, double theta_deg, double u_lid, double cfl,
+                                  double mix, double gamma_min, int dt_rule, int64_t n_steps, hipStream_t s, double* J,
+                                  double* grad, std::string& err, bool use_scratch)
+{
+    TParams P;
+    std::vector<D3> geo;
+    tangent_params(nx, ny, re, n, theta_deg, u_lid, cfl, mix, gamma_min, dt_rule, P, geo);
+    const size_t elems = tangent_workspace_elems(nx, ny);
+    D3* work = nullptr;
+    hipError_t e = hipSuccess;
+    if (use_scratch) {
+        if (elems > tangent_scratch_capacity_elems()) {
+            err = "grid too large for the scratch array";
+            return hipErrorInvalidValue;
+        }
+        void* p = nullptr;
+        e = scratch_of_current_device(&p, err);
+        if (e != hipSuccess) return e;
+        work = static_cast<D3*>(p);
+    } else {
+        e = hipMalloc(reinterpret_cast<void**>(&work), elems * sizeof(D3));
+        if (e != hipSuccess) {
+            err = std::string("gradient: ") + hipGetErrorString(e);
+            return e;
+        }
+    }
+    e = tangent_run(P, geo, work, n_steps, s, J, grad, err);
+    if (!use_scratch) (void)hipFree(work);
+    return e;
 }
 
 }  // namespace ifd

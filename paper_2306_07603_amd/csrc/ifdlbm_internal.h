@@ -114,10 +114,15 @@ hipError_t launch_probe(int prec, const void* f, const CavityDesc* desc, int n_c
                         double* partial, const int32_t* first, const int32_t* count, double* rec, uint32_t* rec_count,
                         int capacity, hipStream_t s);
 
-// Tangent-linear kinetic energy of one cavity after n_steps (see ifdlbm_gradient).
+// Tangent-linear kinetic energy of one cavity after n_steps (see ifdlbm_gradient).  The work arrays
+// (tangent_workspace_elems values of three-component duals) are allocated and freed inside the call, or with
+// use_scratch taken from the current device's file-scope scratch array, which holds
+// tangent_scratch_capacity_elems of them.
 hipError_t tangent_kinetic_energy(int nx, int ny, double re, double n, double theta_deg, double u_lid, double cfl,
                                   double mix, double gamma_min, int dt_rule, int64_t n_steps, hipStream_t s, double* J,
-                                  double* grad, std::string& err);
+                                  double* grad, std::string& err, bool use_scratch);
+size_t tangent_workspace_elems(int nx, int ny);
+size_t tangent_scratch_capacity_elems();
 
 // Reverse (discrete adjoint) sweep of one cavity's step in FP64.  A state is
 // 9 planes of f-hat deviations then the Lambda plane, [k][j][i] packed, as

@@ -112,6 +112,8 @@ def lib():
         L.ifdlbm_info.argtypes = [_H, ctypes.POINTER(ifdlbm_info_t)]
         L.ifdlbm_gradient.argtypes = [ctypes.POINTER(ifdlbm_cavity), ctypes.POINTER(ifdlbm_options), ctypes.c_int64,
                                       ctypes.c_int32, _D, _D]
+        L.ifdlbm_gradient_noalloc.argtypes = [ctypes.POINTER(ifdlbm_cavity), ctypes.POINTER(ifdlbm_options),
+                                              ctypes.c_int64, ctypes.c_int32, _D, _D]
         L.ifdlbm_adjoint.argtypes = [ctypes.POINTER(ifdlbm_cavity), ctypes.POINTER(ifdlbm_options), ctypes.c_int64,
                                      ctypes.c_int32, ctypes.c_int32, _D, _D]
         L.ifdlbm_autotune.argtypes = [_H, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _D]
@@ -312,6 +314,17 @@ def ifdlbm_gradient(cavity: Cavity, options: Optional[ifdlbm_options] = None, n_
     grad = np.zeros(3)
     _check(lib().ifdlbm_gradient(ctypes.byref(cavity.c()), ctypes.byref(options), int(n_steps), int(objective),
                                  ctypes.byref(J), _dptr(grad)))
+    return J.value, grad
+
+
+def ifdlbm_gradient_noalloc(cavity: Cavity, options: Optional[ifdlbm_options] = None, n_steps: int = 1,
+                            objective: int = IFDLBM_OBJ_KINETIC_ENERGY):
+    """ifdlbm_gradient with its work arrays in the library's per-GPU scratch array (no device allocation)."""
+    options = options or ifdlbm_default_options()
+    J = ctypes.c_double()
+    grad = np.zeros(3)
+    _check(lib().ifdlbm_gradient_noalloc(ctypes.byref(cavity.c()), ctypes.byref(options), int(n_steps),
+                                         int(objective), ctypes.byref(J), _dptr(grad)))
     return J.value, grad
 
 
