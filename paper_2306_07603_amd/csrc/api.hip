@@ -61,9 +61,6 @@ constexpr int kSegCandidates[] = {128, 96, 80, 72, 64, 56, 48, 40, 32, 24, 16, 8
 constexpr int kMinSegRows = 8;
 constexpr int kTargetItems = 4096;
 constexpr int kXcds = 8;   // MI355X: workgroups are dealt to the 8 XCDs in turn
-#ifndef IFD_ITEM_ORDER
-#define IFD_ITEM_ORDER 1   // 0: longest first over all items; 1: per-XCD queues of whole cavities
-#endif
 
 int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
@@ -182,12 +179,6 @@ void order_for_batch(ifdlbm_s* h)
 {
     h->act_sorted.clear();
     if (h->act_items.empty()) return;
-#if IFD_ITEM_ORDER == 0
-    // plain longest-first order over all items
-    h->act_sorted = h->act_items;
-    std::stable_sort(h->act_sorted.begin(), h->act_sorted.end(),
-                     [](const StripItem& x, const StripItem& y) { return item_cost(x) > item_cost(y); });
-#else
     struct Group {
         int64_t cost;
         size_t first, count;
@@ -214,7 +205,6 @@ void order_for_batch(ifdlbm_s* h)
     const StripItem empty{0, 0, 0, 0, 0, -1};
     for (size_t r = 0; r < rows; ++r)
         for (int x = 0; x < kXcds; ++x) h->act_sorted.push_back(r < queue[x].size() ? queue[x][r] : empty);
-#endif
 }
 
 int rebuild_worklists(ifdlbm_s* h)

@@ -36,41 +36,12 @@ constexpr int kPad = 2;                          // LDS columns beyond the wave 
 constexpr int kRowLds = kWaveLanes + 2 * kPad;   // elements of one LDS exchange row
 constexpr int kRing = 5;                         // ring slots: rows t - 4 .. t
 
-// Rows per loop trip (1: rings moved by one slot per row; kRing: renamed) and
-// the smallest number of waves per SIMD the register allocation must allow:
-// FP32 arithmetic, FP64 storage and arithmetic, FP32 storage with FP64
-// arithmetic.  Build-time knobs for tuning.
-#ifndef IFD_FUSED_UNROLL_F32
-#define IFD_FUSED_UNROLL_F32 5
-#endif
-#ifndef IFD_FUSED_UNROLL_F64
-#define IFD_FUSED_UNROLL_F64 5
-#endif
-#ifndef IFD_FUSED_UNROLL_MIXED
-#define IFD_FUSED_UNROLL_MIXED 5
-#endif
-#ifndef IFD_FUSED_ONE_PATH
-#define IFD_FUSED_ONE_PATH 1   // 1: every wave takes the wall-aware code (half the code, a select per point)
-#endif
-#ifndef IFD_SRF_D64
-#define IFD_SRF_D64 1   // FP32SRF: the non-equilibrium part e - g of stage A in FP64 (0: in FP32)
-#endif
-#ifndef IFD_STORE_AUX
-#define IFD_STORE_AUX 0   // cache-policy bits of the state stores (2: non-temporal)
-#endif
-#ifndef IFD_FUSED_WAVES_F32
-#define IFD_FUSED_WAVES_F32 2
-#endif
-#ifndef IFD_FUSED_WAVES_F64
-#define IFD_FUSED_WAVES_F64 1
-#endif
+// Waves per SIMD the register allocation must allow: two with FP32 arithmetic (256 VGPRs each), one with
+// FP64 arithmetic (its rings and stage temporaries take about 430 registers).
 template <int PREC>
 struct Tuning {
     static constexpr bool kWide = sizeof(typename Storage<PREC>::T) == 8;
-    static constexpr bool kMixed = kWide && sizeof(typename Storage<PREC>::F) == 4;
-    static constexpr int kUnroll = kMixed ? IFD_FUSED_UNROLL_MIXED : (kWide ? IFD_FUSED_UNROLL_F64 : IFD_FUSED_UNROLL_F32);
-    static constexpr int kWaves = kWide ? IFD_FUSED_WAVES_F64 : IFD_FUSED_WAVES_F32;
-    static_assert(kUnroll == 1 || kUnroll == kRing, "the ring is renamed only over a full turn");
+    static constexpr int kWaves = kWide ? 1 : 2;
 };
 
 // Dword 3 of a raw buffer resource on the gfx9 family (CDNA): 32-bit data
@@ -96,7 +67,7 @@ template <> struct Buf<double> {
     __device__ static void st(double v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
     {
         using W = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0u, 0));
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(W, v), r, vo, so, IFD_STORE_AUX);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(W, v), r, vo, so, 0);
     }
 };
 template <> struct Buf<float> {
@@ -106,7 +77,7 @@ template <> struct Buf<float> {
     }
     __device__ static void st(float v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
     {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, vo, so, IFD_STORE_AUX);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, vo, so, 0);
     }
 };
 template <> struct Buf<__half> {
@@ -116,7 +87,7 @@ template <> struct Buf<__half> {
     }
     __device__ static void st(__half v, __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so)
     {
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, vo, so, IFD_STORE_AUX);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, vo, so, 0);
     }
 };
 
@@ -162,12 +133,12 @@ constexpr bool moves_down(int k) { return cyk(k) < 0; }
 // term vanishes).  Byte offsets into an LDS row: a1/a2/f1 of the first
 // member of each pair, a2m the far point of the mirrored member (whose a1
 // and f1 are the pair's f1 and a1).
-template <typename T, bool EDGE>
+template <typename T>
 struct XiLane {
     uint32_t own;           // this lane's column
     uint32_t a1[3], a2[3], f1[3], a2m[3];
     T ad[3];                // |d| of the pairs
-    bool edge1, edge3;      // EDGE: second upwind point outside the grid (first-order point, Eq. 2.7 at walls)
+    bool edge1, edge3;      // second upwind point outside the grid (first-order point, Eq. 2.7 at walls)
     bool edge_p[3], edge_m[3];
 
     __device__ __forceinline__ XiLane(int lane, int i, int nx, T s)
@@ -183,15 +154,11 @@ struct XiLane {
             f1[c] = pos ? own + E : own - E;
             a2[c] = pos ? own - 2 * E : own + 2 * E;
             a2m[c] = pos ? own + 2 * E : own - 2 * E;
-            if (EDGE) {
-                edge_p[c] = pos ? i == 1 : i == nx - 2;
-                edge_m[c] = pos ? i == nx - 2 : i == 1;
-            }
+            edge_p[c] = pos ? i == 1 : i == nx - 2;
+            edge_m[c] = pos ? i == nx - 2 : i == 1;
         }
-        if (EDGE) {
-            edge1 = i == 1;
-            edge3 = i == nx - 2;
-        }
+        edge1 = i == 1;
+        edge3 = i == nx - 2;
     }
 };
 
@@ -293,7 +260,7 @@ __device__ __forceinline__ void residual_add(const T (&gn)[9], const T (&old)[3]
 // One work item.  Register ring slot of row t - d at unrolled phase R:
 // (R + 5 - d) % 5 for f-bar+ and lambda (d = 0..4), (R + 10 - d) % 5 for
 // f(t + dt/2) (d = 2..6); with one row per trip R is 0 and the rings move.
-template <int PREC, bool RES, bool EDGE, bool IMPL>
+template <int PREC, bool RES, bool IMPL>
 struct March {
     using S = Storage<PREC>;
     using T = typename S::T;
@@ -321,7 +288,7 @@ struct March {
     // (uniform over the wave) comes by a scalar load, on the scalar counter, so that waiting for it does not
     // also wait for the vector loads of the next row in flight
     const __attribute__((address_space(4))) T* geo;
-    XiLane<T, EDGE> xl;
+    XiLane<T> xl;
     __amdgpu_buffer_rsrc_t rf_in, rf_out, rl_in, rl_out;
     uint32_t fpb;          // bytes per distribution plane
     uint32_t skey, ckey;   // stochastic rounding keys
@@ -488,7 +455,7 @@ struct March {
                 a2 = lds_at(row, pos ? xl.own - 2 * E : xl.own + 2 * E);
                 f1 = lds_at(row, pos ? xl.own + E : xl.own - E);
                 w = T(1);
-                if (EDGE) edge = pos ? xl.edge1 : xl.edge3;
+                edge = pos ? xl.edge1 : xl.edge3;
             } else {
                 const int pr = (k == 2 || k == 4) ? 0 : ((k == 5 || k == 7) ? 1 : 2);
                 const bool first = k == 2 || k == 5 || k == 6;
@@ -496,11 +463,11 @@ struct March {
                 a2 = lds_at(row, first ? xl.a2[pr] : xl.a2m[pr]);
                 f1 = lds_at(row, first ? xl.f1[pr] : xl.a1[pr]);
                 w = xl.ad[pr];
-                if (EDGE) edge = first ? xl.edge_p[pr] : xl.edge_m[pr];
+                edge = first ? xl.edge_p[pr] : xl.edge_m[pr];
             }
             T o;
             if constexpr (kDiffForm<T>) {
-                const T d1 = c0 - a1, d2 = (EDGE && edge) ? d1 : a1 - a2;
+                const T d1 = c0 - a1, d2 = edge ? d1 : a1 - a2;
                 o = base[k] - w * mx.apply_diff(f1 - a1, d1, d2);
                 if (moves_up(k)) {
                     const T b1 = c0 - ring[S1][k], b2 = elo ? b1 : ring[S1][k] - ring[S0][k];
@@ -511,7 +478,7 @@ struct March {
                     o = o - my.apply_diff(ring[S1][k] - ring[S3][k], b1, b2);
                 }
             } else {
-                if (EDGE) a2 = edge ? T(2) * a1 - c0 : a2;
+                a2 = edge ? T(2) * a1 - c0 : a2;
                 o = base[k] - w * mx.apply(a2, a1, c0, f1);
                 if (moves_up(k)) o = o - my.apply(ring[S0][k], ring[S1][k], c0, ring[S3][k]);
                 if (moves_down(k)) o = o - my.apply(ring[S4][k], ring[S3][k], c0, ring[S1][k]);
@@ -523,7 +490,7 @@ struct March {
 
     // Rows outside [1, ny-2] of a ring take the linear extrapolation 2 a1 - c0,
     // which turns the second-order one-sided difference into the first-order
-    // one (the eta counterpart of the EDGE columns).
+    // one (the eta counterpart of the wall columns of XiLane).
     template <int S0, int S1, int S2, int S3, int S4>
     __device__ __forceinline__ void eta_ghosts(T (&ring)[kRing][9], bool lo, bool hi)
     {
@@ -567,7 +534,7 @@ struct March {
             }
             if (fetch_next) fetch(t + 1);   // consumed by the next row (ten vector-memory loads)
             V l;
-            if constexpr (S::kExactFinal && IFD_SRF_D64) {
+            if constexpr (S::kExactFinal) {
                 // e - g in FP64 from the exact stored g: at low shear the non-equilibrium part is far below
                 // an FP32 ulp of g, and Step (2) raises it to the power (n - 1) / 2
                 double gd[9], dd[9], Pd, uxd, uyd;
@@ -737,58 +704,21 @@ struct March {
         if constexpr (kMetricRing) am[sg(R, 0)] = geo[min(max(t - 1, 0), ny - 1)];
     }
 
-    __device__ __forceinline__ void rotate()
-    {
-        // one row per trip: move every ring one slot so that phase 0 fits the next row
-        T tg[9], tf[9];
-        const V tl = lam[0];
-        const T ta = am[0];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            tg[k] = gbp[0][k];
-            tf[k] = fh[0][k];
-        }
-#pragma unroll
-        for (int r = 0; r < kRing - 1; ++r) {
-            lam[r] = lam[r + 1];
-            am[r] = am[r + 1];
-#pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                gbp[r][k] = gbp[r + 1][k];
-                fh[r][k] = fh[r + 1][k];
-            }
-        }
-        lam[kRing - 1] = tl;
-        am[kRing - 1] = ta;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            gbp[kRing - 1][k] = tg[k];
-            fh[kRing - 1][k] = tf[k];
-        }
-    }
-
+    // Rows are unrolled over a full turn of the rings, so that slots are renamed, not moved.
     __device__ __forceinline__ void march(int t_begin, int t_end)
     {
-        if constexpr (Tuning<PREC>::kUnroll == kRing) {
 #pragma unroll 1
-            for (int t = t_begin;; t += kRing) {
-                row<0>(t);
-                if (t + 1 > t_end) break;
-                row<1>(t + 1);
-                if (t + 2 > t_end) break;
-                row<2>(t + 2);
-                if (t + 3 > t_end) break;
-                row<3>(t + 3);
-                if (t + 4 > t_end) break;
-                row<4>(t + 4);
-                if (t + 5 > t_end) break;
-            }
-        } else {
-#pragma unroll 1
-            for (int t = t_begin; t <= t_end; ++t) {
-                row<0>(t);
-                rotate();
-            }
+        for (int t = t_begin;; t += kRing) {
+            row<0>(t);
+            if (t + 1 > t_end) break;
+            row<1>(t + 1);
+            if (t + 2 > t_end) break;
+            row<2>(t + 2);
+            if (t + 3 > t_end) break;
+            row<3>(t + 3);
+            if (t + 4 > t_end) break;
+            row<4>(t + 4);
+            if (t + 5 > t_end) break;
         }
     }
 };
@@ -804,11 +734,7 @@ __global__ __launch_bounds__(kWaveLanes, Tuning<PREC>::kWaves) void k_fused(Step
     double acc[kPartials];
 #pragma unroll
     for (int q = 0; q < kPartials; ++q) acc[q] = 0.0;
-    // waves that hold column 1 or nx-2 take the first-order one-sided points (Eq. 2.7 at walls)
-    if (IFD_FUSED_ONE_PATH || it.i0 <= 5 || it.i1 >= c.nx - 5)
-        March<PREC, RES, true, IMPL>(a, it, c, sh, acc);
-    else
-        March<PREC, RES, false, IMPL>(a, it, c, sh, acc);
+    March<PREC, RES, IMPL>(a, it, c, sh, acc);
     if (RES) {
         // wavefront sum in a fixed order
 #pragma unroll
