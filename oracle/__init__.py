@@ -29,20 +29,23 @@ DT_CONTRAVARIANT, DT_CARTESIAN = 0, 1
 LAMBDA_LAGGED, LAMBDA_IMPLICIT = 0, 1
 
 
-def compile_source(src: str, out: str) -> str:
-    """gcc -O2 -ffp-contract=off, serial FP64: the oracle's only build recipe."""
+def compile_source(src: str, out: str, defines=()) -> str:
+    """gcc -O2 -ffp-contract=off, serial FP64: the oracle's only build recipe (defines: -D options, such as
+    ORC_COMPLEX_STEP for the complex-step build)."""
     tmp = out + ".tmp%d" % os.getpid()
     subprocess.check_call([
         "gcc", "-O2", "-ffp-contract=off", "-std=c99", "-D_DEFAULT_SOURCE", "-Wall", "-Wextra",
-        "-I", _HERE, "-fPIC", "-shared", "-o", tmp, src, "-lm"])
+        *["-D" + d for d in defines], "-I", _HERE, "-fPIC", "-shared", "-o", tmp, src, "-lm"])
     os.replace(tmp, out)
     return out
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle library in place."""
+    """Compile the oracle library in place, and its complex-step build."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         compile_source(_SRC, _LIB)
+    from . import complex_step
+    complex_step.build(force)
     return _LIB
 
 

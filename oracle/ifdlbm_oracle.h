@@ -27,6 +27,15 @@
 extern "C" {
 #endif
 
+/* The oracle's arithmetic type: double, or with ORC_COMPLEX_STEP a complex double, for the complex-step
+   derivative of its outputs with respect to a parameter (J(x + i h) = J(x) + i h J'(x) + O(h^2)). */
+#ifdef ORC_COMPLEX_STEP
+#include <complex.h>
+typedef double _Complex orc_real;
+#else
+typedef double orc_real;
+#endif
+
 /* bc_mode values.  ORC_CAVITY is the paper's problem (Eq. 1.5).  The two
  * periodic modes are test-only geometries (theta must be 90 degrees) used to
  * pin the oracle against closed forms and exact conservation. */
@@ -34,14 +43,14 @@ enum { ORC_CAVITY = 0, ORC_COUETTE = 1, ORC_PERIODIC = 2 };
 
 typedef struct {
     int    nx, ny;      /* nodes along xi and eta, boundary nodes included   */
-    double re;          /* generalised Reynolds number, Eq. (2.15.1), L = 1  */
-    double n;           /* power-law index, Eq. (1.4)                        */
-    double theta_deg;   /* top angle of the isosceles trapezoid, (0, 90]     */
-    double u_lid;       /* lid speed u0, Eq. (1.5); may be negative in tests */
-    double cfl;         /* dt = cfl * min(dxi, deta) / c, c = 1              */
-    double mix;         /* weight of the central scheme in Eq. (2.5)         */
-    double rho0;        /* constant density rho_0 of Eq. (2.8)               */
-    double gamma_min;   /* floor of the shear rate in Eq. (1.4)              */
+    orc_real re;          /* generalised Reynolds number, Eq. (2.15.1), L = 1  */
+    orc_real n;           /* power-law index, Eq. (1.4)                        */
+    orc_real theta_deg;   /* top angle of the isosceles trapezoid, (0, 90]     */
+    orc_real u_lid;       /* lid speed u0, Eq. (1.5); may be negative in tests */
+    orc_real cfl;         /* dt = cfl * min(dxi, deta) / c, c = 1              */
+    orc_real mix;         /* weight of the central scheme in Eq. (2.5)         */
+    orc_real rho0;        /* constant density rho_0 of Eq. (2.8)               */
+    orc_real gamma_min;   /* floor of the shear rate in Eq. (1.4)              */
     int    bc_mode;     /* ORC_CAVITY, ORC_COUETTE or ORC_PERIODIC           */
     int    dt_rule;     /* ORC_DT_CONTRAVARIANT or ORC_DT_CARTESIAN          */
     int    lambda_mode; /* ORC_LAMBDA_LAGGED or ORC_LAMBDA_IMPLICIT          */
@@ -63,75 +72,77 @@ enum { ORC_DT_CONTRAVARIANT = 0, ORC_DT_CARTESIAN = 1 };
 
 /* Derived constants of one run. */
 typedef struct {
-    double dxi, deta;   /* grid spacings of the computational square          */
-    double dt;          /* time step                                          */
-    double K;           /* consistency coefficient from Eq. (2.15.1)          */
-    double cot;         /* 1/tan(theta), exactly 0 at 90 degrees              */
-    double lam0;        /* initial relaxation time U L / (Re c_s^2)           */
+    orc_real dxi, deta;   /* grid spacings of the computational square          */
+    orc_real dt;          /* time step                                          */
+    orc_real K;           /* consistency coefficient from Eq. (2.15.1)          */
+    orc_real cot;         /* 1/tan(theta), exactly 0 at 90 degrees              */
+    orc_real lam0;        /* initial relaxation time U L / (Re c_s^2)           */
 } orc_derived;
 
 /* Returns 0, or -1 when the parameters are outside the method's domain. */
 int  orc_derive(const orc_params* p, orc_derived* d);
 
-/* D2Q9 constants of Eq. (2.9): c_k (as doubles), omega_k, omegabar_k. */
-void orc_lattice(double cx[9], double cy[9], double w[9], double wbar[9], double* cs2);
+/* D2Q9 constants of Eq. (2.9): c_k (as orc_reals), omega_k, omegabar_k. */
+void orc_lattice(orc_real cx[9], orc_real cy[9], orc_real w[9], orc_real wbar[9], orc_real* cs2);
 
 /* Eq. (2.8): incompressible equilibrium at (P, u). */
-void orc_equilibrium(double P, double ux, double uy, double rho0, double feq[9]);
+void orc_equilibrium(orc_real P, orc_real ux, orc_real uy, orc_real rho0, orc_real feq[9]);
 
 /* Eqs. (2.10)-(2.11): velocity and pressure from any of f, f-bar, f-hat. */
-void orc_moments(const double f[9], double rho0, double* P, double* ux, double* uy);
+void orc_moments(const orc_real f[9], orc_real rho0, orc_real* P, orc_real* ux, orc_real* uy);
 
 /* Per-node conversions of the calculational process (Section 4):
  * Eq. (2.18) f from f-hat, Eq. (2.17) f from f-bar, Eqs. (2.15)-(2.16) the
  * post-collision f-hat+ and f-bar+, and Step (2), lambda from the
  * non-equilibrium part by Eqs. (2.12)-(2.14) and (1.4) given the lambda that
  * produced f-hat. */
-void   orc_f_from_fhat_node(const double fh[9], const double feq[9], double lam, double dt, double f[9]);
-void   orc_f_from_fbar(const double fb[9], const double feq[9], double lam, double dt, double f[9]);
-void   orc_collide(const double fh[9], const double feq[9], double lam, double dt,
-                   double fhat_plus[9], double fbar_plus[9]);
-double orc_relaxation_time(const double fh[9], const double feq[9], double lam_old, double dt,
-                           double K, double n, double gamma_min);
+void   orc_f_from_fhat_node(const orc_real fh[9], const orc_real feq[9], orc_real lam, orc_real dt, orc_real f[9]);
+void   orc_f_from_fbar(const orc_real fb[9], const orc_real feq[9], orc_real lam, orc_real dt, orc_real f[9]);
+void   orc_collide(const orc_real fh[9], const orc_real feq[9], orc_real lam, orc_real dt,
+                   orc_real fhat_plus[9], orc_real fbar_plus[9]);
+orc_real orc_relaxation_time(const orc_real fh[9], const orc_real feq[9], orc_real lam_old, orc_real dt,
+                           orc_real K, orc_real n, orc_real gamma_min);
 /* The implicit reading: the lambda for which orc_relaxation_time returns the
  * lambda it was given (a fixed point), found by bisection. */
-double orc_relaxation_time_implicit(const double fh[9], const double feq[9], double dt, double K, double n,
-                                    double gamma_min);
+orc_real orc_relaxation_time_implicit(const orc_real fh[9], const orc_real feq[9], orc_real dt, orc_real K, orc_real n,
+                                    orc_real gamma_min);
 
 /* Eq. (3.8.1): physical position of node (i, j). */
-void orc_node_xy(const orc_params* p, int i, int j, double* x, double* y);
+void orc_node_xy(const orc_params* p, int i, int j, orc_real* x, orc_real* y);
 
 /* Eqs. (3.2)-(3.8.2): contravariant velocities (c_k,xi , c_k,eta) at (i, j),
  * and the Jacobian J of Eq. (3.3). */
-void orc_contravariant(const orc_params* p, int i, int j, double cxi[9], double ceta[9], double* J);
+void orc_contravariant(const orc_params* p, int i, int j, orc_real cxi[9], orc_real ceta[9], orc_real* J);
 
 /* Mixed-difference transport term c_k,xi dPhi_k/dxi + c_k,eta dPhi_k/deta of
  * Eqs. (2.5)-(2.7) and (3.4) at interior node (i, j), for population k of
  * the nine-plane field Phi. */
-double orc_stream_term(const orc_params* p, const double* Phi, int k, int i, int j);
+orc_real orc_stream_term(const orc_params* p, const orc_real* Phi, int k, int i, int j);
 
 /* Step (1): rest state plus moving lid; F = f-hat = f_eq, Lam = lambda_0. */
-int  orc_init(const orc_params* p, double* F, double* Lam);
+int  orc_init(const orc_params* p, orc_real* F, orc_real* Lam);
 
 /* Steps (2)-(8), nsteps times, in place.  res_u / res_p (may be NULL) receive
  * the global relative errors of Eq. (2.19) of the last step.  Returns 0, or
  * -1 on bad parameters, or -2 if the state became non-finite. */
-int  orc_run(const orc_params* p, double* F, double* Lam, long nsteps, double* res_u, double* res_p);
+int  orc_run(const orc_params* p, orc_real* F, orc_real* Lam, long nsteps, orc_real* res_u, orc_real* res_p);
 
 /* Eq. (2.19) between two states: E(u), E(P), and E(P) of the pressure with
  * its spatial mean removed (reading R16). */
-void orc_residuals(const orc_params* p, const double* F_old, const double* F_new,
-                   double* e_u, double* e_p, double* e_p_gauge);
+void orc_residuals(const orc_params* p, const orc_real* F_old, const orc_real* F_new,
+                   orc_real* e_u, orc_real* e_p, orc_real* e_p_gauge);
 
 /* Macroscopic fields u, v, P (each nx*ny, [j][i]) of the state. */
-void orc_fields(const orc_params* p, const double* F, double* u, double* v, double* P);
+void orc_fields(const orc_params* p, const orc_real* F, orc_real* u, orc_real* v, orc_real* P);
 
 /* Step (7), Eq. (2.18): the distribution f from f-hat and the stored lambda. */
-void orc_f_from_fhat(const orc_params* p, const double* F, const double* Lam, double* f);
+void orc_f_from_fhat(const orc_params* p, const orc_real* F, const orc_real* Lam, orc_real* f);
 
 /* Eq. (5.1): kinetic energy 1/2 sum |u|^2 dA over the physical cavity,
  * trapezoid-rule weights in (xi, eta) times the Jacobian J. */
-double orc_kinetic_energy(const orc_params* p, const double* F);
+orc_real orc_kinetic_energy(const orc_params* p, const orc_real* F);
+/* The same into *out (for callers, such as ctypes, that cannot take a complex return value). */
+void orc_kinetic_energy_into(const orc_params* p, const orc_real* F, orc_real* out);
 
 #ifdef __cplusplus
 }

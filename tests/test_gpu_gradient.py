@@ -1,9 +1,9 @@
 """dJ/d(theta, n, U) of the kinetic energy after a fixed number of steps: the
 tangent-linear sweep and the checkpointed discrete adjoint of the library
 against each other (both are the exact derivative of the same discrete map),
-against central differences of the FP64 forward (h = 1e-4) and against
-Richardson-extrapolated differences of the CPU oracle; and the
-torch.autograd.Function over them."""
+against central differences of the FP64 forward (h = 1e-4) and against the
+complex-step derivative of the CPU oracle; and the torch.autograd.Function
+over them."""
 import math
 
 import numpy as np
@@ -44,36 +44,36 @@ def test_gradient_against_central_differences():
         assert err <= 1e-4
 
 
+COMPLEX_STEP_CASES = [
+    # (n_xi, n_eta, Re, n, theta, U, steps, options)
+    (17, 17, 80.0, 1.3, 50.0, 0.1, 120, {}),
+    (17, 17, 100.0, 0.8, 90.0, -0.1, 80, {}),                               # tie of the time-step rule, lid -x
+    (21, 13, 200.0, 0.6, 60.0, 0.1, 60, {"dt_rule": 1, "mix": 0.5}),        # Cartesian time step
+]
+
+
 @pytest.mark.parametrize("method", ["tangent", "adjoint"])
-def test_gradient_against_oracle_differences(method):
-    """17 x 17, 120 steps: Richardson extrapolation of oracle central
-    differences (h and h/2) is accurate to about 1e-9 relative."""
-    n_xi = n_eta = 17
-    re, n, th, u, steps = 80.0, 1.3, 50.0, 0.1, 120
-
-    def ke(theta_deg, nn, uu):
-        p = O.Params(nx=n_xi, ny=n_eta, re=re, n=nn, theta_deg=theta_deg, u_lid=uu)
-        F, L = O.init(p)
-        O.run(p, F, L, steps)
-        return O.kinetic_energy(p, F)
-
-    def deriv(f, h):
-        d1 = (f(h) - f(-h)) / (2 * h)
-        d2 = (f(h / 2) - f(-h / 2)) / h
-        return (4 * d2 - d1) / 3
-
-    ref = [deriv(lambda d: ke(th + math.degrees(d), n, u), 1e-3),
-           deriv(lambda d: ke(th, n + d, u), 1e-3),
-           deriv(lambda d: ke(th, n, u + d), 1e-4)]
+@pytest.mark.parametrize("case", COMPLEX_STEP_CASES, ids=lambda c: "%dx%d_th%g_n%g" % (c[0], c[1], c[4], c[3]))
+def test_gradient_against_oracle_complex_step(method, case):
+    """dJ/d(theta [rad], n, U) of Eq. (5.1) against the complex-step derivative of the CPU oracle (the
+    oracle's source in complex doubles, itself pinned to closed forms and to Richardson differences): both
+    are the derivative of the same discrete map to rounding, 1e-9 relative."""
+    from oracle import complex_step as CS
+    n_xi, n_eta, re, n, th, u, steps, opt = case
+    p = O.Params(nx=n_xi, ny=n_eta, re=re, n=n, theta_deg=th, u_lid=u, rho0=0.0,
+                 dt_rule=opt.get("dt_rule", O.DT_CONTRAVARIANT), mix=opt.get("mix", 0.75))
+    J_ref, g_ref = CS.kinetic_energy_gradient(p, steps)
     cav = M.Cavity(n_xi, n_eta, re, n, th, u)
+    o = M.ifdlbm_default_options(rho0=0.0, **opt)
     if method == "tangent":
-        J, g = M.ifdlbm_gradient(cav, M.ifdlbm_default_options(), steps)
+        J, g = M.ifdlbm_gradient(cav, o, steps)
     else:
-        J, g = M.ifdlbm_adjoint(cav, M.ifdlbm_default_options(), steps, 50)
+        J, g = M.ifdlbm_adjoint(cav, o, steps, 25)
+    assert abs(J - J_ref) <= 1e-12 * J_ref
     for q in range(3):
-        err = abs(g[q] - ref[q]) / abs(ref[q])
-        print("param %d %s %.12e oracle %.12e rel %.2e" % (q, method, g[q], ref[q], err), flush=True)
-        assert err <= 1e-6
+        err = abs(g[q] - g_ref[q]) / abs(g_ref[q])
+        print("param %d %s %.14e complex step %.14e rel %.2e" % (q, method, g[q], g_ref[q], err), flush=True)
+        assert err <= 1e-9
 
 
 @pytest.mark.parametrize("method", ["tangent", "adjoint"])

@@ -16,17 +16,17 @@ MUTATIONS = [
      [C.check_moments_round_trip]),
     ("upwind_printed_third_point", "at(p, plane, i + 2 * di, j + 2 * dj)", "at(p, plane, i + di, j + dj)",
      [C.check_stencils_on_quartics]),
-    ("upwind_side_inverted", "    if (c >= 0.0) {", "    if (c < 0.0) {",
+    ("upwind_side_inverted", "    if (ORC_UPWIND_NONNEG(c)) {", "    if (!ORC_UPWIND_NONNEG(c)) {",
      [C.check_stencils_on_quartics]),
     ("one_sided_fallback_wrong", "upwind = (c0 - m1) / h;", "upwind = (c0 - m1) / (2.0 * h);",
      [C.check_metric_exact_on_linear_fields]),
     ("metric_xi_y_sign", "xi_y = -x_eta / jac", "xi_y = x_eta / jac",
      [C.check_metric_exact_on_linear_fields]),
-    ("jacobian_missing", "double xi_x = y_eta / jac", "double xi_x = y_eta",
+    ("jacobian_missing", "orc_real xi_x = y_eta / jac", "orc_real xi_x = y_eta",
      [C.check_metric_exact_on_linear_fields]),
     ("map_sign", "*x = 2.0 * C * xi * eta + xi - C * eta + C;", "*x = 2.0 * C * xi * eta + xi + C * eta + C;",
      [C.check_geometry_matches_paper]),
-    ("shear_rate_missing_factor_two", "double gamma2 = 2.0 * (Dxx", "double gamma2 = 1.0 * (Dxx",
+    ("shear_rate_missing_factor_two", "orc_real gamma2 = 2.0 * (Dxx", "orc_real gamma2 = 1.0 * (Dxx",
      [C.check_relaxation_time_power_law, C.check_couette_power_law]),
     ("strain_uses_lambda_twice", "-sxx / (lam_old * CS2)", "-sxx / (2.0 * lam_old * CS2)",
      [C.check_relaxation_time_power_law, C.check_couette_power_law]),
@@ -43,9 +43,9 @@ MUTATIONS = [
     ("lattice_diagonals_swapped", "static const double CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};",
      "static const double CX[9] = {0, 1, 0, -1, 0, -1, 1, -1, 1};",
      [C.check_lattice_matches_paper]),
-    ("energy_edge_weights", "? 0.5 : 1.0;\n            double wj", "? 1.0 : 1.0;\n            double wj",
+    ("energy_edge_weights", "? 0.5 : 1.0;\n            orc_real wj", "? 1.0 : 1.0;\n            orc_real wj",
      [C.check_kinetic_energy_weights]),
-    ("implicit_strain_scale", "double s = 2.0 * lam + dt;", "double s = lam + dt;",
+    ("implicit_strain_scale", "orc_real s = 2.0 * lam + dt;", "orc_real s = lam + dt;",
      [C.check_implicit_lambda]),
     ("implicit_bracket_direction", "            lo = mid;\n        else", "            hi = mid;\n        else",
      [C.check_implicit_lambda]),
