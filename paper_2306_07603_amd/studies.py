@@ -6,6 +6,10 @@ python -m paper_2306_07603_amd.studies <name> [--out FILE] [options]
              aperiodic) of the cavities whose regime the paper reports, from the
              centre velocity and the kinetic energy of Eq. (5.1) recorded on the
              device, classified by the library's spectral classifier.
+  regime_factors
+             two cases the paper reports periodic, under one-factor changes of
+             the readings the paper leaves open: grid nodes, time-step rule,
+             central weight of Eq. (2.5).
   precision  the 257 x 257 precision sweep: steady states in FP64, and the FP32
              storage modes run as many steps, velocity error against FP64.
   lag        Step (2) with the lagged lambda of Section 3 against its implicit
@@ -103,6 +107,73 @@ def regime(n_side: int = 257, time_units: float = 3000.0, every: int = 50, preci
     return {"study": "regime", "n_side": n_side, "time_units": time_units, "every": every, "precision": precision,
             "mix": o.mix,
             "steady_tol": steady_tol, "steps": steps, "seconds": time.time() - t0, "cases": out}
+
+
+# One-factor variants of the regime study: (label, nodes per side, options).  The base is the library's
+# default reading (257 nodes for the paper's 256 x 256 grid, contravariant time step R11, central weight
+# 0.75 of Eq. 2.5); each variant changes one of them.
+REGIME_FACTORS = [
+    ("base", 257, {}),
+    ("256 nodes", 256, {}),
+    ("Cartesian time step", 257, {"dt_rule": M.IFDLBM_DT_CARTESIAN}),
+    ("central weight 0.9", 257, {"mix": 0.9}),
+    ("central weight 0.5", 257, {"mix": 0.5}),
+]
+# the two cases the paper reports periodic where the base reading finds a steady flow
+REGIME_FACTOR_CASES = [(60.0, 1.0, 2500.0), (75.0, 1.5, 6000.0)]
+
+
+def regime_factors(time_units: float = 10000.0, every: int = 50, precision: str = "fp32srf",
+                   chunk: int = 100000, steady_tol: float = 1e-4) -> dict:
+    """The cases of REGIME_FACTOR_CASES under each variant of REGIME_FACTORS, for `time_units` each.  Variants
+    with the same options share a handle; the handles step in turn, each on its own stream, so that their
+    small launches overlap on the GPU.  Records and classification as in regime()."""
+    groups = {}
+    for label, side, opt in REGIME_FACTORS:
+        key = tuple(sorted(opt.items()))
+        groups.setdefault(key, []).extend((label, side, case) for case in REGIME_FACTOR_CASES)
+    runs = []
+    for key, members in groups.items():
+        o = M.ifdlbm_default_options(precision=precision, residual_every=1000, graph_steps=1000, **dict(key))
+        cav = [M.Cavity(side, side, re, n, th, 0.1) for _, side, (th, n, re) in members]
+        h = M.ifdlbm_create(cav, o)
+        dts = [M.ifdlbm_time_step(h, c) for c in range(len(cav))]
+        steps = int(time_units / min(dts)) // 1000 * 1000 + 1000
+        cap = steps // every + 2
+        M.ifdlbm_record(h, every, cap)
+        runs.append({"h": h, "members": members, "dts": dts, "steps": steps, "cap": cap, "done": 0,
+                     "options": dict(key)})
+    t0 = time.time()
+    while any(r["done"] < r["steps"] for r in runs):
+        for r in runs:
+            k = min(chunk, r["steps"] - r["done"])
+            if k > 0:
+                M.ifdlbm_step(r["h"], k)
+                r["done"] += k
+        for r in runs:
+            M.ifdlbm_sync(r["h"])
+        log("regime factors: %s steps, %.0f s" % ([r["done"] for r in runs], time.time() - t0))
+    out = []
+    for r in runs:
+        h = r["h"]
+        ru, _ = M.ifdlbm_get_residuals(h)
+        for c, (label, side, (th, n, re)) in enumerate(r["members"]):
+            st, u, v, ke = M.ifdlbm_get_record(h, c, r["cap"])
+            half = st.size // 2
+            dt_sample = every * r["dts"][c]
+            rk = M.ifdlbm_classify(ke[half:], dt_sample, steady_tol) if np.all(np.isfinite(ke[half:])) else None
+            rc_ = M.ifdlbm_classify(u[half:], dt_sample, steady_tol) if np.all(np.isfinite(u[half:])) else None
+            out.append({"variant": label, "n_side": side, "options": r["options"], "theta": th, "n": n, "re": re,
+                        "dt": r["dts"][c], "time_units": float(st[-1] * r["dts"][c]) if st.size else 0.0,
+                        "status": M.ifdlbm_status(h, c), "ke": rk, "u_centre": rc_, "res_u_final": float(ru[c])})
+            log("%-22s theta %g n %.1f Re %g: %.0f time units, ke %s (rel amp %.2e, f %.4g), u %s (rel amp %.2e, "
+                "f %.4g), E(u) %.1e"
+                % (label, th, n, re, out[-1]["time_units"], rk["name"] if rk else "non-finite",
+                   rk["rel_amplitude"] if rk else 0, rk["f_main"] if rk else 0, rc_["name"] if rc_ else "non-finite",
+                   rc_["rel_amplitude"] if rc_ else 0, rc_["f_main"] if rc_ else 0, ru[c]))
+        h.close()
+    return {"study": "regime_factors", "time_units": time_units, "every": every, "precision": precision,
+            "steady_tol": steady_tol, "seconds": time.time() - t0, "cases": out}
 
 
 def precision(n_side: int = 257, tol: float = 1e-8, max_steps: int = 2000000,
@@ -288,7 +359,7 @@ def adjoint(n_side: int = 129, steps: int = 20000, checkpoint_every: int = 500) 
     return out
 
 
-STUDIES = {"regime": regime, "precision": precision, "lag": lag, "stress": stress, "unsteady": unsteady,
+STUDIES = {"regime": regime, "regime_factors": regime_factors, "precision": precision, "lag": lag, "stress": stress, "unsteady": unsteady,
            "adjoint": adjoint}
 
 
@@ -303,7 +374,7 @@ def main(argv=None) -> int:
     ap.add_argument("--mix", type=float, default=None, help="regime: central weight of Eq. (2.5)")
     args = ap.parse_args(argv)
     kw = {}
-    if args.time_units is not None and args.name in ("regime", "stress"):
+    if args.time_units is not None and args.name in ("regime", "regime_factors", "stress"):
         kw["time_units"] = args.time_units
     if args.name == "regime" and args.cases:
         kw["cases"] = [int(x) for x in args.cases.split(",")]
