@@ -185,7 +185,8 @@ struct WaveLds {
                                       // f-bar of row ny-2 for the lid row of the half step
     T wb[2][9];                       // f-bar of columns 1 and nx-2 at the current half-step row
     T wc[2][9];                       // f-hat(t+dt) of columns 1 and nx-2 at the current full-step row
-    T gx[NG][kWaveLanes];             // stored f-hat of the stage-C row, written by the buffer unit
+    T gx[2][NG][kWaveLanes];          // stored f-hat of the next two stage-C rows (slot: row parity), written by
+                                      // the buffer unit one row ahead of its use
 };
 
 // Compiler-level memory barrier: no memory operation is moved across it, and
@@ -376,18 +377,25 @@ struct March {
     }
 
     // Exact final update: the stored f-hat of `row` copied by the buffer unit
-    // straight into sh.gx, so that no registers are held while it is in flight.
-    // The compiler does not track these copies: the reader waits on the
-    // vector-memory counter itself (wait_vm).
+    // straight into sh.gx (slot row & 1), so that no registers are held while it
+    // is in flight.  It is issued one row ahead of its stage C, before the fetch
+    // of the next row: the vector-memory counter completes in issue order, so
+    // the wait for that fetch, which stage A of the next row needs anyway, also
+    // covers the copy.  Where no fetch follows it (the rows past ny - 1), stage
+    // C waits on the counter itself (wait_vm).
     __device__ __forceinline__ void reload_lds(int row)
     {
         static_assert(sizeof(F) == 4, "the LDS copy moves one dword per lane");
         const uint32_t vo = foff(row);
+        auto& slot = sh.gx[row & 1];
 #pragma unroll
         for (int k = 0; k < 9; ++k)
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rf_in, (__attribute__((address_space(3))) void*)&sh.gx[k][0], 4u,
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rf_in, (__attribute__((address_space(3))) void*)&slot[k][0], 4u,
                                                     vo, (uint32_t)k * fpb, 0, 0);
     }
+
+    // stage C runs at row p of the march
+    __device__ __forceinline__ bool c_row(int p) const { return p >= j0 && p < j1 && p >= 1 && p <= ny - 2; }
 
     // old moments of row `row` (residual only)
     __device__ __forceinline__ void old_moments(int row, T (&m)[3]) const
@@ -510,9 +518,10 @@ struct March {
     __device__ __forceinline__ void row(int t)
     {
         const int p = t - 4;
-        const bool do_c = p >= j0 && p < j1 && p >= 1 && p <= ny - 2;
-        // exact final update: the stored f-hat of row p goes to LDS first, ahead of the fetch of row t + 1,
-        // so that stage C's wait for it leaves that fetch in flight
+        const bool do_c = c_row(p);
+        // exact final update: the stored f-hat of the next row's stage C goes to LDS ahead of the fetch of row
+        // t + 1, whose wait in the next row's stage A covers it
+        const bool reload_next = S::kExactFinal && c_row(p + 1);
         const bool fetch_next = t <= ny - 1 && t + 1 <= t_last;
 
         // ------------------------------------------------------------ A: row t
@@ -529,7 +538,7 @@ struct March {
                 for (int k = 0; k < 9; ++k) asm volatile("" ::"v"(g[k]));
                 asm volatile("" ::"v"(lam_old));
                 mem_order();
-                if (do_c) reload_lds(p);
+                if (reload_next) reload_lds(p + 1);
                 mem_order();
             }
             if (fetch_next) fetch(t + 1);   // consumed by the next row (ten vector-memory loads)
@@ -567,7 +576,7 @@ struct March {
             Buf<L>::st(L(l), rl_out, out_col && t >= j0 && t < j1 ? loff(t) : kDroppedOffset, 0u);
         } else if constexpr (S::kExactFinal) {
             mem_order();
-            if (do_c) reload_lds(p);
+            if (reload_next) reload_lds(p + 1);
             mem_order();
         }
 
@@ -631,13 +640,13 @@ struct March {
 #pragma unroll
                 for (int k = 0; k < 9; ++k) hp[k] = sh.hp[hs][k][lane];
                 transport<sf(R, 6), sf(R, 5), sf(R, 4), sf(R, 3), sf(R, 2)>(fh, hp, mx, my, p == 1, p == ny - 2, gn);
-                if (fetch_next)
-                    wait_vm<10>();   // the LDS copy of row p was followed by the ten loads of row t + 1
-                else
-                    wait_vm<0>();
+                // with a stage A in this row, its wait for the fetch of row t (issued after the copy of row p)
+                // has covered the copy; the rows past ny - 1 wait here
+                if (t > ny - 1) wait_vm<0>();
+                const auto& gx = sh.gx[p & 1];
 #pragma unroll
                 for (int k = 0; k < 9; ++k) {
-                    fin[k] = (double)S::cvt(sh.gx[k][lane], k) + (double)gn[k];
+                    fin[k] = (double)S::cvt(gx[k][lane], k) + (double)gn[k];
                     gn[k] = T(fin[k]);   // the FP32 value, for the wall extrapolation and the residual
                 }
             } else {
