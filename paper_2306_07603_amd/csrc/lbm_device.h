@@ -244,22 +244,59 @@ __device__ __forceinline__ void moments(const T g[9], T& P, T& ux, T& uy)
 
 // Eq. (2.8) minus omega_k rho0, with the second-order term over 2 c_s^4:
 // e_0 = -5/3 P - 2/3 |u|^2, e_k = omega_k (3 P + 3 c.u + 4.5 (c.u)^2 - 1.5 |u|^2).
+// In FP64 the velocity term is written with a = 1.5 c.u as 2 a (a + 1) =
+// a (2 a + 2): every constant of that form is an inline operand of the FP64
+// FMA (3 and 4.5 are not, and VOP3 takes no literal), and c.u of a lattice
+// direction is a signed sum of a_x = 1.5 u_x and a_y = 1.5 u_y, so no product
+// with a zero velocity component is formed.  equilibrium_k is the same
+// arithmetic population by population.
+template <typename T>
+__device__ __forceinline__ T eq_velocity_term(T cu)   // FP32: 3 c.u + 4.5 (c.u)^2
+{
+    return cu * (T(3) + T(4.5) * cu);
+}
+__device__ __forceinline__ double eq_velocity_term_a(double a)   // FP64: a = 1.5 c.u
+{
+    return a * __builtin_fma(a, 2.0, 2.0);
+}
+
+// a = 1.5 c_k.u of population k (FP64) from a_x = 1.5 u_x and a_y = 1.5 u_y
+__device__ __forceinline__ double eq_a(int k, double ax, double ay)
+{
+    switch (k) {
+    case 1: return ax;
+    case 2: return ay;
+    case 3: return -ax;
+    case 4: return -ay;
+    case 5: return ax + ay;
+    case 6: return ay - ax;
+    case 7: return -(ax + ay);
+    default: return ax - ay;
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ void equilibrium(T P, T ux, T uy, T e[9])
 {
     const T uu = ux * ux + uy * uy;
     const T base = T(3) * P - T(1.5) * uu;
     const T w1 = T(1) / T(9), w5 = T(1) / T(36);
-    auto q = [&](T cu) { return base + cu * (T(3) + T(4.5) * cu); };
     e[0] = T(-5) / T(3) * P - T(2) / T(3) * uu;
-    e[1] = w1 * q(ux);
-    e[2] = w1 * q(uy);
-    e[3] = w1 * q(-ux);
-    e[4] = w1 * q(-uy);
-    e[5] = w5 * q(ux + uy);
-    e[6] = w5 * q(uy - ux);
-    e[7] = w5 * q(-ux - uy);
-    e[8] = w5 * q(ux - uy);
+    if constexpr (std::is_same<T, double>::value) {
+        const double ax = __builtin_fma(0.5, ux, ux), ay = __builtin_fma(0.5, uy, uy);
+#pragma unroll
+        for (int k = 1; k < 9; ++k) e[k] = (k < 5 ? w1 : w5) * (base + eq_velocity_term_a(eq_a(k, ax, ay)));
+    } else {
+        auto q = [&](T cu) { return base + eq_velocity_term(cu); };
+        e[1] = w1 * q(ux);
+        e[2] = w1 * q(uy);
+        e[3] = w1 * q(-ux);
+        e[4] = w1 * q(-uy);
+        e[5] = w5 * q(ux + uy);
+        e[6] = w5 * q(uy - ux);
+        e[7] = w5 * q(-ux - uy);
+        e[8] = w5 * q(ux - uy);
+    }
 }
 
 // Population k of Eq. (2.8) alone (same arithmetic as equilibrium()).
@@ -269,8 +306,15 @@ __device__ __forceinline__ T equilibrium_k(T P, T ux, T uy, int k)
     const T uu = ux * ux + uy * uy;
     const T base = T(3) * P - T(1.5) * uu;
     const T w = k < 5 ? T(1) / T(9) : T(1) / T(36);
-    const T cu = T(cxk(k)) * ux + T(cyk(k)) * uy;
-    return k == 0 ? T(-5) / T(3) * P - T(2) / T(3) * uu : w * (base + cu * (T(3) + T(4.5) * cu));
+    if (k == 0) return T(-5) / T(3) * P - T(2) / T(3) * uu;
+    if constexpr (std::is_same<T, double>::value) {
+        const double ax = __builtin_fma(0.5, ux, ux), ay = __builtin_fma(0.5, uy, uy);
+        return w * (base + eq_velocity_term_a(eq_a(k, ax, ay)));
+    } else {
+        const T cu = k == 1 ? ux : k == 2 ? uy : k == 3 ? -ux : k == 4 ? -uy
+                   : k == 5 ? ux + uy : k == 6 ? uy - ux : k == 7 ? -ux - uy : ux - uy;
+        return w * (base + eq_velocity_term(cu));
+    }
 }
 
 // 1/x for x > 0: v_rcp_f32 (1 ulp) in FP32; v_rcp_f64 refined by two Newton
