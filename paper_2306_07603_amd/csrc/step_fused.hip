@@ -35,6 +35,12 @@ namespace {
 constexpr int kPad = 2;                          // LDS columns beyond the wave on each side
 constexpr int kRowLds = kWaveLanes + 2 * kPad;   // elements of one LDS exchange row
 constexpr int kRing = 5;                         // ring slots: rows t - 4 .. t
+// Exact final update: stage C needs the stored f-hat of its row again.  Stage A
+// keeps populations 0 .. kGxRing - 1 of it in a lane-private LDS ring; the
+// buffer unit copies the others back from memory (by then the row has left L2).
+// Four ring populations fill the LDS of two waves per SIMD (20 240 bytes per
+// wave, 8 waves in the 160 KiB of a CU).
+constexpr int kGxRing = 4;
 
 // Waves per SIMD the register allocation must allow: two with FP32 arithmetic (256 VGPRs each), one with
 // FP64 arithmetic (its rings and stage temporaries take about 430 registers).
@@ -185,8 +191,9 @@ struct WaveLds {
                                       // f-bar of row ny-2 for the lid row of the half step
     T wb[2][9];                       // f-bar of columns 1 and nx-2 at the current half-step row
     T wc[2][9];                       // f-hat(t+dt) of columns 1 and nx-2 at the current full-step row
-    T gx[2][NG][kWaveLanes];          // stored f-hat of the next two stage-C rows (slot: row parity), written by
-                                      // the buffer unit one row ahead of its use
+    T gr[NG ? kRing : 0][kGxRing][kWaveLanes];   // stored f-hat of populations 0 .. kGxRing - 1, rows t-4 .. t
+    T gx[NG ? 9 - kGxRing : 0][kWaveLanes];      // stored f-hat of the other populations of the stage-C row,
+                                                 // written by the buffer unit
 };
 
 // Compiler-level memory barrier: no memory operation is moved across it, and
@@ -376,26 +383,19 @@ struct March {
         ln_ = Buf<L>::ld(rl_in, loff(row), 0u);
     }
 
-    // Exact final update: the stored f-hat of `row` copied by the buffer unit
-    // straight into sh.gx (slot row & 1), so that no registers are held while it
-    // is in flight.  It is issued one row ahead of its stage C, before the fetch
-    // of the next row: the vector-memory counter completes in issue order, so
-    // the wait for that fetch, which stage A of the next row needs anyway, also
-    // covers the copy.  Where no fetch follows it (the rows past ny - 1), stage
-    // C waits on the counter itself (wait_vm).
+    // Exact final update: populations kGxRing .. 8 of the stored f-hat of `row`
+    // copied by the buffer unit straight into sh.gx, so that no registers are
+    // held while they are in flight.  The compiler does not track these copies:
+    // the reader waits on the vector-memory counter itself (wait_vm).
     __device__ __forceinline__ void reload_lds(int row)
     {
         static_assert(sizeof(F) == 4, "the LDS copy moves one dword per lane");
         const uint32_t vo = foff(row);
-        auto& slot = sh.gx[row & 1];
 #pragma unroll
-        for (int k = 0; k < 9; ++k)
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rf_in, (__attribute__((address_space(3))) void*)&slot[k][0], 4u,
-                                                    vo, (uint32_t)k * fpb, 0, 0);
+        for (int k = kGxRing; k < 9; ++k)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rf_in, (__attribute__((address_space(3))) void*)&sh.gx[k - kGxRing][0],
+                                                    4u, vo, (uint32_t)k * fpb, 0, 0);
     }
-
-    // stage C runs at row p of the march
-    __device__ __forceinline__ bool c_row(int p) const { return p >= j0 && p < j1 && p >= 1 && p <= ny - 2; }
 
     // old moments of row `row` (residual only)
     __device__ __forceinline__ void old_moments(int row, T (&m)[3]) const
@@ -518,10 +518,9 @@ struct March {
     __device__ __forceinline__ void row(int t)
     {
         const int p = t - 4;
-        const bool do_c = c_row(p);
-        // exact final update: the stored f-hat of the next row's stage C goes to LDS ahead of the fetch of row
-        // t + 1, whose wait in the next row's stage A covers it
-        const bool reload_next = S::kExactFinal && c_row(p + 1);
+        const bool do_c = p >= j0 && p < j1 && p >= 1 && p <= ny - 2;
+        // exact final update: the copies of row p go to LDS first, ahead of the fetch of row t + 1, so that
+        // stage C's wait for them leaves that fetch in flight
         const bool fetch_next = t <= ny - 1 && t + 1 <= t_last;
 
         // ------------------------------------------------------------ A: row t
@@ -538,7 +537,7 @@ struct March {
                 for (int k = 0; k < 9; ++k) asm volatile("" ::"v"(g[k]));
                 asm volatile("" ::"v"(lam_old));
                 mem_order();
-                if (reload_next) reload_lds(p + 1);
+                if (do_c) reload_lds(p);
                 mem_order();
             }
             if (fetch_next) fetch(t + 1);   // consumed by the next row (ten vector-memory loads)
@@ -571,12 +570,15 @@ struct March {
                 // exact final update: only the collision increment of f-hat+ (Eq. 2.15); the stored g is added
                 // in FP64 at stage C
                 sh.hp[hs][k][lane] = S::kExactFinal ? b_hat * d[k] : g[k] + b_hat * d[k];
+                if constexpr (S::kExactFinal) {
+                    if (k < kGxRing) sh.gr[hs][k][lane] = g[k];
+                }
             }
             lam[sg(R, 0)] = l;
             Buf<L>::st(L(l), rl_out, out_col && t >= j0 && t < j1 ? loff(t) : kDroppedOffset, 0u);
         } else if constexpr (S::kExactFinal) {
             mem_order();
-            if (reload_next) reload_lds(p + 1);
+            if (do_c) reload_lds(p);
             mem_order();
         }
 
@@ -640,13 +642,14 @@ struct March {
 #pragma unroll
                 for (int k = 0; k < 9; ++k) hp[k] = sh.hp[hs][k][lane];
                 transport<sf(R, 6), sf(R, 5), sf(R, 4), sf(R, 3), sf(R, 2)>(fh, hp, mx, my, p == 1, p == ny - 2, gn);
-                // with a stage A in this row, its wait for the fetch of row t (issued after the copy of row p)
-                // has covered the copy; the rows past ny - 1 wait here
-                if (t > ny - 1) wait_vm<0>();
-                const auto& gx = sh.gx[p & 1];
+                if (fetch_next)
+                    wait_vm<10>();   // the LDS copies of row p were followed by the ten loads of row t + 1
+                else
+                    wait_vm<0>();
 #pragma unroll
                 for (int k = 0; k < 9; ++k) {
-                    fin[k] = (double)S::cvt(gx[k][lane], k) + (double)gn[k];
+                    const T g = k < kGxRing ? sh.gr[hs][k][lane] : sh.gx[k - kGxRing][lane];
+                    fin[k] = (double)S::cvt(g, k) + (double)gn[k];
                     gn[k] = T(fin[k]);   // the FP32 value, for the wall extrapolation and the residual
                 }
             } else {
