@@ -92,8 +92,10 @@ def measured_record(precision: str, what: str, segment_rows):
 
 def binding_limit(hbm_frac: float, valu):
     """The limit the kernel runs into: "valu" when the VALU issue fraction of the
-    same launches exceeds the HBM fraction (the metric's), else "hbm"; None
-    without a VALU figure."""
+    same launches exceeds the memory fraction `hbm_frac`, else "hbm"; None
+    without a VALU figure.  The memory fraction is the measured traffic rate
+    over the device-copy rate of the same run when both are known, else the
+    algorithmic rate over the HBM peak."""
     if not valu:
         return None
     return "valu" if valu["frac"] > hbm_frac else "hbm"
@@ -140,6 +142,29 @@ def cpu_baseline(specs, steps: int):
             "cpu_model": model, "host_cpus": os.cpu_count(),
             "sample": "serial FP64 oracle, %d steps of one cavity of each side (65, 129, 257, 513) of the batch, "
                       "%.1f s" % (steps, dt)}
+
+
+def copy_ceiling(stream, reps: int = 10) -> dict:
+    """Rate of a plain device copy of 2 GiB (torch copy_, read + write bytes over
+    the HIP-event time on `stream`): the practical ceiling of a stream that reads
+    and writes each byte once, on the box the step was timed on."""
+    import torch
+    n = (2 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(reps):
+        b.copy_(a)
+    end.record(stream)
+    end.synchronize()
+    gbs = 2.0 * n * 4 * reps / (start.elapsed_time(end) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return {"achieved": gbs, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "what": "device copy of 2 GiB, read + write bytes over HIP-event time, %d copies" % reps}
 
 
 def copy_calibration() -> int:
@@ -290,6 +315,13 @@ def main() -> int:
         valu = {"achieved": rate, "peak": VALU_PEAK_GINST, "unit": "G wave64 VALU instructions/s",
                 "frac": rate / VALU_PEAK_GINST, "insts_per_launch": insts}
     h.close()
+    # the memory side of the same launches: the recorded L2-egress bytes per launch over the measured launch
+    # time, against the rate a plain device copy reaches on this machine
+    copy = copy_ceiling(stream)
+    log("device copy: %.0f GB/s" % copy["achieved"])
+    traffic = measured_record(args.precision, "bytes", seg_rows)
+    traffic_gbs = traffic / (kernel_ms * 1e-3) / 1e9 if traffic else None
+    mem_frac = traffic_gbs / copy["achieved"] if traffic_gbs else achieved / HBM_PEAK_GBS
 
     plain = None
     if args.plain_steps > 0:
@@ -328,12 +360,15 @@ def main() -> int:
                    "diverged_cavities": diverged, "diverged_indices": bad, "warmup_steps_run": warmup_run,
                    "segment_rows": seg_rows, "autotune_steps": args.autotune_steps, **ex},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_record(args.precision, "bytes", seg_rows),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_counters": "FETCH_SIZE + WRITE_SIZE per launch, scaled by a plain copy: bytes between "
                                          "L2 and the memory fabric, Infinity Cache hits included",
+                     "traffic_gbs": traffic_gbs,
+                     "traffic_frac_of_copy": traffic_gbs / copy["achieved"] if traffic_gbs else None,
+                     "copy_ceiling": copy,
                      "event_ms_per_launch": kernel_ms, "alg_bytes_per_launch": alg_bytes,
                      "alg_bytes_per_node": info["alg_bytes_per_node"], "valu": valu,
-                     "binding": binding_limit(achieved / HBM_PEAK_GBS, valu)},
+                     "binding": binding_limit(mem_frac, valu)},
         "fp64_plain": plain,
         "fp64_batched": fp64_batched,
         "other_modes": other or None,
