@@ -187,6 +187,17 @@ int ifdlbm_get_fields(ifdlbm_t* h, int32_t cav, double* u, double* v, double* p)
    after it.  With the handle's own stream the call waits until the arrays are written. */
 int ifdlbm_get_fields_device(ifdlbm_t* h, int32_t cav, void* u, void* v, void* p, int32_t dtype);
 
+/* The stochastic rounding of the FP32SR and FP32SRF storage modes (their encode of a new state value) on its
+   own, for tests of the rounding step: out[i] is the FP32 value those modes store for the FP64 value v[i] with
+   the 16 random bits r16[i] & 0xFFFF.  The bits are added at the top of the 29 significand bits that FP32 drops,
+   which are then truncated, so the result is the FP32 neighbour of larger magnitude with probability
+   floor(2^16 * dropped fraction) / 2^16 over uniform bits, and v itself where v is an FP32 value.  In a step the
+   bits come from a counter-based hash of (step, cavity, node); here the caller passes them in.  v, r16 and out
+   are caller-owned device arrays of n elements (no handle); the call runs on hip_stream (NULL: the null stream)
+   and returns when out is written.  Results are specified for values whose truncation stays in the FP32 normal
+   range.  Errors: EINVAL (n < 0, or a NULL array with n > 0), EDEVICE. */
+int ifdlbm_round_stochastic_device(const double* v, const uint32_t* r16, float* out, int64_t n, void* hip_stream);
+
 /* Kinetic energy of Eq. (5.1) of cavity cav: 1/2 sum |u|^2 over the physical area, trapezoid weights in
    (xi, eta) times the Jacobian J = 1 + 2 eta cot(theta). */
 int ifdlbm_kinetic_energy(ifdlbm_t* h, int32_t cav, double* energy);

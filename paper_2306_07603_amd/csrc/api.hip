@@ -1228,6 +1228,17 @@ const char* ifdlbm_strerror(int code)
 
 const char* ifdlbm_last_error(void) { return g_last_error.c_str(); }
 
+static int ifdlbm_round_stochastic_device_impl(const double* v, const uint32_t* r16, float* out, int64_t n,
+                                               void* hip_stream)
+{
+    if (n < 0) return fail(IFDLBM_EINVAL, "round_stochastic_device: n < 0");
+    if (n > 0 && (!v || !r16 || !out)) return fail(IFDLBM_EINVAL, "round_stochastic_device: NULL array");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    IFD_HIP(launch_round_stochastic(v, r16, out, n, s));
+    IFD_HIP(hipStreamSynchronize(s));
+    return IFDLBM_OK;
+}
+
 #ifndef IFD_SOURCE_DIGEST
 #error "IFD_SOURCE_DIGEST: build the library with paper_2306_07603_amd/_build.py"
 #endif
@@ -1268,6 +1279,11 @@ int ifdlbm_run_to_steady(ifdlbm_t* h, double tol, int64_t max_steps, int64_t* st
 int ifdlbm_get_fields_device(ifdlbm_t* h, int32_t cav, void* u, void* v, void* p, int32_t dtype)
 {
     IFD_GUARD(ifdlbm_get_fields_device_impl(h, cav, u, v, p, dtype));
+}
+
+int ifdlbm_round_stochastic_device(const double* v, const uint32_t* r16, float* out, int64_t n, void* hip_stream)
+{
+    IFD_GUARD(ifdlbm_round_stochastic_device_impl(v, r16, out, n, hip_stream));
 }
 
 int ifdlbm_get_fields(ifdlbm_t* h, int32_t cav, double* u, double* v, double* p)

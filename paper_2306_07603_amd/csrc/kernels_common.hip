@@ -339,6 +339,23 @@ hipError_t launch_probe(int prec, const void* f, const CavityDesc* desc, int n_c
     return hipGetLastError();
 }
 
+// The stochastic rounding of the FP32SR / FP32SRF encode on given values and
+// random numbers (the low 16 bits of r16).
+__global__ void k_round_stochastic(const double* v, const uint32_t* r16, float* out, int64_t n)
+{
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+        out[q] = round_stochastic(v[q], r16[q] & 0xFFFFu);
+}
+
+hipError_t launch_round_stochastic(const double* v, const uint32_t* r16, float* out, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_round_stochastic, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, s, v, r16,
+                       out, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_energy(int prec, const void* f, const CavityDesc*, const double*, int, const CavityDesc& hd,
                          double* partial, hipStream_t s)
 {

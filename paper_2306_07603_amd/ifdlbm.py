@@ -105,6 +105,8 @@ def lib():
         L.ifdlbm_get_fields.argtypes = [_H, ctypes.c_int32, _D, _D, _D]
         L.ifdlbm_get_fields_device.argtypes = [_H, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                ctypes.c_int32]
+        L.ifdlbm_round_stochastic_device.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                                     ctypes.c_void_p]
         L.ifdlbm_kinetic_energy.argtypes = [_H, ctypes.c_int32, _D]
         L.ifdlbm_get_state.argtypes = [_H, ctypes.c_int32, _D, _D]
         L.ifdlbm_set_state.argtypes = [_H, ctypes.c_int32, _D, _D]
@@ -270,6 +272,19 @@ def ifdlbm_get_fields_device(h: Handle, cav: int, u, v, p) -> None:
         assert t.is_contiguous() and t.numel() == h.shape(cav)[0] * h.shape(cav)[1] and t.element_size() == u.element_size()
     _check(lib().ifdlbm_get_fields_device(h.ptr, cav, ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(v.data_ptr()),
                                           ctypes.c_void_p(p.data_ptr()), dt))
+
+
+def ifdlbm_round_stochastic_device(v, r16, out, stream=None) -> None:
+    """The storage modes' stochastic rounding of FP64 to FP32 on device tensors: v float64, r16 int32 (its low 16
+    bits are the random number), out float32, all contiguous with the same number of elements; runs on `stream`
+    (a torch stream, default the current one) and returns when out is written."""
+    import torch
+    assert v.dtype == torch.float64 and r16.dtype == torch.int32 and out.dtype == torch.float32
+    assert v.is_contiguous() and r16.is_contiguous() and out.is_contiguous()
+    assert v.numel() == r16.numel() == out.numel() and v.is_cuda and r16.is_cuda and out.is_cuda
+    s = (stream or torch.cuda.current_stream()).cuda_stream
+    _check(lib().ifdlbm_round_stochastic_device(ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(r16.data_ptr()),
+                                                ctypes.c_void_p(out.data_ptr()), v.numel(), ctypes.c_void_p(s)))
 
 
 def ifdlbm_kinetic_energy(h: Handle, cav: int) -> float:
