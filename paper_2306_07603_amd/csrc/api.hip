@@ -1228,6 +1228,11 @@ const char* ifdlbm_strerror(int code)
 
 const char* ifdlbm_last_error(void) { return g_last_error.c_str(); }
 
+namespace ifd {
+// out[i] = round_stochastic(v[i], r16[i] & 0xFFFF) for i < n (device arrays; kernels_common.hip)
+hipError_t launch_round_stochastic(const double* v, const uint32_t* r16, float* out, int64_t n, hipStream_t s);
+}
+
 static int ifdlbm_round_stochastic_device_impl(const double* v, const uint32_t* r16, float* out, int64_t n,
                                                void* hip_stream)
 {

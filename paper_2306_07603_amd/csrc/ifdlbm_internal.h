@@ -107,9 +107,6 @@ hipError_t launch_state_in(int prec, void* f, void* l, const CavityDesc& hd, dou
 hipError_t launch_energy(int prec, const void* f, const CavityDesc* desc, const double* geo, int cav_index,
                          const CavityDesc& hd, double* partial, hipStream_t s);
 
-// out[i] = round_stochastic(v[i], r16[i] & 0xFFFF) for i < n (device arrays).
-hipError_t launch_round_stochastic(const double* v, const uint32_t* r16, float* out, int64_t n, hipStream_t s);
-
 // Probe record of every cavity (centre velocity and kinetic energy of Eq. 5.1)
 // into slot *rec_count % capacity, then *rec_count + 1; blocks [0, nb) are all
 // node blocks, first/count their range per cavity, partial nb doubles.
