@@ -18,6 +18,9 @@ using namespace ifd;
 
 namespace ifd {
 
+// out[i] = round_stochastic(v[i], r16[i] & 0xFFFF) for i < n (device arrays; kernels_common.hip)
+hipError_t launch_round_stochastic(const double* v, const uint32_t* r16, float* out, int64_t n, hipStream_t s);
+
 thread_local std::string g_last_error;
 
 // Records the text of the last error of this thread and returns code.
@@ -1227,11 +1230,6 @@ const char* ifdlbm_strerror(int code)
 }
 
 const char* ifdlbm_last_error(void) { return g_last_error.c_str(); }
-
-namespace ifd {
-// out[i] = round_stochastic(v[i], r16[i] & 0xFFFF) for i < n (device arrays; kernels_common.hip)
-hipError_t launch_round_stochastic(const double* v, const uint32_t* r16, float* out, int64_t n, hipStream_t s);
-}
 
 static int ifdlbm_round_stochastic_device_impl(const double* v, const uint32_t* r16, float* out, int64_t n,
                                                void* hip_stream)
