@@ -121,7 +121,20 @@ struct MixedWeights {
     // cancellation what the differences keep (an error of order one ulp of f
     // per step that does not average out over a steady run).
     __device__ __forceinline__ T apply_diff(T df, T d1, T d2) const { return (wc * d1 - wa2 * d2) + wf * df; }
+    // The same from backward differences B(m) = x(m) - x(m - 1) along the
+    // upwind direction: with n = B at the point (d1), f = B one further
+    // upwind (d2) and o = B one downwind (df = n + o),
+    // (eps + 3 (1 - eps)) n - (1 - eps) f + eps o.
+    __device__ __forceinline__ T apply_back(T n, T f, T o) const { return ((wc + wf) * n - wa2 * f) + wf * o; }
 };
+
+// x of lane l - 1 in lane l (lane 0 reads 0): a wavefront shift of the data-parallel primitives, folded by the
+// compiler into the instruction that uses it.
+__device__ __forceinline__ float lane_below(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x138 /* wave_shr:1 */,
+                                                                0xF, 0xF, true));
+}
 
 // Mixed differences from differences first where the distributions are FP32.
 template <typename T> constexpr bool kDiffForm = sizeof(T) == 4;
@@ -136,9 +149,17 @@ constexpr bool moves_down(int k) { return cyk(k) < 0; }
 // (Eqs. 3.2-3.8.2): d = 1 for k = 1, -1 for k = 3, and for the pairs
 // (2, 4), (5, 7), (6, 8) the second member has minus the first's d.  The
 // upwind side follows sign(d) (ties: the c >= 0 side; there |d| = 0 and the
-// term vanishes).  Byte offsets into an LDS row: a1/a2/f1 of the first
-// member of each pair, a2m the far point of the mirrored member (whose a1
-// and f1 are the pair's f1 and a1).
+// term vanishes).  Byte offsets into an LDS row.
+// FP64 arithmetic (rows of values): a1/a2/f1 of the first member of each
+// pair, a2m the far point of the mirrored member (whose a1 and f1 are the
+// pair's f1 and a1); ad = |d|.
+// FP32 arithmetic (rows of backward differences B(m) = x(m) - x(m - 1)): the
+// member with d >= 0 reads near B(l), far B(l - 1) and other B(l + 1), the
+// member with d < 0 near B(l + 1), far B(l + 2) and other B(l).  a1 is the
+// first member's near (the second's other), f1 the first's other (the
+// second's near), a2 and a2m the two far points, which at a wall-adjacent
+// column are the near ones (the first-order point of Eq. 2.7); ad = d,
+// signed.
 template <typename T>
 struct XiLane {
     uint32_t own;           // this lane's column
@@ -155,13 +176,22 @@ struct XiLane {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const bool pos = d[c] >= T(0);
-            ad[c] = pos ? d[c] : -d[c];
-            a1[c] = pos ? own - E : own + E;
-            f1[c] = pos ? own + E : own - E;
-            a2[c] = pos ? own - 2 * E : own + 2 * E;
-            a2m[c] = pos ? own + 2 * E : own - 2 * E;
             edge_p[c] = pos ? i == 1 : i == nx - 2;
             edge_m[c] = pos ? i == nx - 2 : i == 1;
+            if constexpr (kDiffForm<T>) {
+                const uint32_t far_p = i == 1 ? own : own - E, far_m = i == nx - 2 ? own + E : own + 2 * E;
+                ad[c] = d[c];
+                a1[c] = pos ? own : own + E;
+                f1[c] = pos ? own + E : own;
+                a2[c] = pos ? far_p : far_m;
+                a2m[c] = pos ? far_m : far_p;
+            } else {
+                ad[c] = pos ? d[c] : -d[c];
+                a1[c] = pos ? own - E : own + E;
+                f1[c] = pos ? own + E : own - E;
+                a2[c] = pos ? own - 2 * E : own + 2 * E;
+                a2m[c] = pos ? own + 2 * E : own - 2 * E;
+            }
         }
         edge1 = i == 1;
         edge3 = i == nx - 2;
@@ -446,17 +476,57 @@ struct March {
                                               const MixedWeights<T>& my, bool elo, bool ehi, T (&out)[9])
     {
         auto& xs = sh.xs;
+        if constexpr (kDiffForm<T>) {
+            // the backward difference of each lane's value, its left neighbour's taken across the wavefront
 #pragma unroll
-        for (int k = 1; k < 9; ++k) xs[k - 1][lane + kPad] = ring[S2][k];
+            for (int k = 1; k < 9; ++k) xs[k - 1][lane + kPad] = ring[S2][k] - lane_below(ring[S2][k]);
+        } else {
+#pragma unroll
+            for (int k = 1; k < 9; ++k) xs[k - 1][lane + kPad] = ring[S2][k];
+        }
         wave_sync();
         out[0] = base[0];
 #pragma unroll
         for (int k = 1; k < 9; ++k) {
             const T* row = xs[k - 1];
             const T c0 = ring[S2][k];
+            constexpr uint32_t E = sizeof(T);
+            if constexpr (kDiffForm<T>) {
+                // xi term from the backward differences: near, far and other point of this population's upwind
+                // side (XiLane), signed by d
+                T n, f, o, w;
+                bool minus;   // out = base - w t (d >= 0 member of a pair, k = 1) or base + w t
+                if (k == 1 || k == 3) {
+                    const bool pos = k == 1;
+                    n = lds_at(row, pos ? xl.own : xl.own + E);
+                    f = (pos ? xl.edge1 : xl.edge3) ? n : lds_at(row, pos ? xl.own - E : xl.own + 2 * E);
+                    o = lds_at(row, pos ? xl.own + E : xl.own);
+                    w = T(1);
+                    minus = pos;
+                } else {
+                    const int pr = (k == 2 || k == 4) ? 0 : ((k == 5 || k == 7) ? 1 : 2);
+                    const bool first = k == 2 || k == 5 || k == 6;
+                    n = lds_at(row, first ? xl.a1[pr] : xl.f1[pr]);
+                    f = lds_at(row, first ? xl.a2[pr] : xl.a2m[pr]);
+                    o = lds_at(row, first ? xl.f1[pr] : xl.a1[pr]);
+                    w = xl.ad[pr];
+                    minus = first;
+                }
+                const T t = mx.apply_back(n, f, o);
+                T r = minus ? base[k] - w * t : base[k] + w * t;
+                if (moves_up(k)) {
+                    const T b1 = c0 - ring[S1][k], b2 = elo ? b1 : ring[S1][k] - ring[S0][k];
+                    r = r - my.apply_diff(ring[S3][k] - ring[S1][k], b1, b2);
+                }
+                if (moves_down(k)) {
+                    const T b1 = c0 - ring[S3][k], b2 = ehi ? b1 : ring[S3][k] - ring[S4][k];
+                    r = r - my.apply_diff(ring[S1][k] - ring[S3][k], b1, b2);
+                }
+                out[k] = r;
+                continue;
+            }
             T a1, a2, f1, w;
             bool edge = false;
-            constexpr uint32_t E = sizeof(T);
             if (k == 1 || k == 3) {
                 const bool pos = k == 1;
                 a1 = lds_at(row, pos ? xl.own - E : xl.own + E);
@@ -473,24 +543,10 @@ struct March {
                 w = xl.ad[pr];
                 edge = first ? xl.edge_p[pr] : xl.edge_m[pr];
             }
-            T o;
-            if constexpr (kDiffForm<T>) {
-                const T d1 = c0 - a1, d2 = edge ? d1 : a1 - a2;
-                o = base[k] - w * mx.apply_diff(f1 - a1, d1, d2);
-                if (moves_up(k)) {
-                    const T b1 = c0 - ring[S1][k], b2 = elo ? b1 : ring[S1][k] - ring[S0][k];
-                    o = o - my.apply_diff(ring[S3][k] - ring[S1][k], b1, b2);
-                }
-                if (moves_down(k)) {
-                    const T b1 = c0 - ring[S3][k], b2 = ehi ? b1 : ring[S3][k] - ring[S4][k];
-                    o = o - my.apply_diff(ring[S1][k] - ring[S3][k], b1, b2);
-                }
-            } else {
-                a2 = edge ? T(2) * a1 - c0 : a2;
-                o = base[k] - w * mx.apply(a2, a1, c0, f1);
-                if (moves_up(k)) o = o - my.apply(ring[S0][k], ring[S1][k], c0, ring[S3][k]);
-                if (moves_down(k)) o = o - my.apply(ring[S4][k], ring[S3][k], c0, ring[S1][k]);
-            }
+            a2 = edge ? T(2) * a1 - c0 : a2;
+            T o = base[k] - w * mx.apply(a2, a1, c0, f1);
+            if (moves_up(k)) o = o - my.apply(ring[S0][k], ring[S1][k], c0, ring[S3][k]);
+            if (moves_down(k)) o = o - my.apply(ring[S4][k], ring[S3][k], c0, ring[S1][k]);
             out[k] = o;
         }
         wave_sync();
