@@ -126,6 +126,11 @@ struct MixedWeights {
     // upwind (d2) and o = B one downwind (df = n + o),
     // (eps + 3 (1 - eps)) n - (1 - eps) f + eps o.
     __device__ __forceinline__ T apply_back(T n, T f, T o) const { return ((wc + wf) * n - wa2 * f) + wf * o; }
+    // r minus the same, as three multiply-adds into r
+    __device__ __forceinline__ T sub_back(T r, T n, T f, T o) const
+    {
+        return __builtin_fmaf(-(wc + wf), n, __builtin_fmaf(wa2, f, __builtin_fmaf(-wf, o, r)));
+    }
 };
 
 // x of lane l - 1 in lane l (lane 0 reads 0): a wavefront shift of the data-parallel primitives, folded by the
@@ -514,13 +519,16 @@ struct March {
                 }
                 const T t = mx.apply_back(n, f, o);
                 T r = minus ? base[k] - w * t : base[k] + w * t;
+                // eta term: the backward differences along the upwind direction from the ring (the row below for
+                // populations moving up, the row above for those moving down); at rows 1 and ny - 2 the far one is
+                // the near one
                 if (moves_up(k)) {
-                    const T b1 = c0 - ring[S1][k], b2 = elo ? b1 : ring[S1][k] - ring[S0][k];
-                    r = r - my.apply_diff(ring[S3][k] - ring[S1][k], b1, b2);
+                    const T nb = c0 - ring[S1][k];
+                    r = my.sub_back(r, nb, elo ? nb : ring[S1][k] - ring[S0][k], ring[S3][k] - c0);
                 }
                 if (moves_down(k)) {
-                    const T b1 = c0 - ring[S3][k], b2 = ehi ? b1 : ring[S3][k] - ring[S4][k];
-                    r = r - my.apply_diff(ring[S1][k] - ring[S3][k], b1, b2);
+                    const T nb = c0 - ring[S3][k];
+                    r = my.sub_back(r, nb, ehi ? nb : ring[S3][k] - ring[S4][k], ring[S1][k] - c0);
                 }
                 out[k] = r;
                 continue;
@@ -706,7 +714,10 @@ struct March {
                 for (int k = 0; k < 9; ++k) {
                     const T g = k < kGxRing ? sh.gr[hs][k][lane] : sh.gx[k - kGxRing][lane];
                     fin[k] = (double)S::cvt(g, k) + (double)gn[k];
-                    gn[k] = T(fin[k]);   // the FP32 value, for the wall extrapolation and the residual
+                }
+                if (RES || walls_c || (p == 1 && j0 == 0) || (p == ny - 2 && j1 == ny)) {
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) gn[k] = T(fin[k]);
                 }
             } else {
                 const int hs = hslot(p);
