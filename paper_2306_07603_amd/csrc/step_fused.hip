@@ -17,10 +17,16 @@
 // xi-direction stencils read neighbour lanes through one LDS row per
 // population, at per-lane addresses that already point at the upwind side
 // (the sign of the contravariant velocity of Eq. (3.2) is fixed per column
-// and population), so no operand is selected after the read.  The rows of
-// the march are unrolled five times so that ring slots are renamed, not
-// moved.  The halo costs 8 of 64 lanes across xi and 8 + 4 recomputed rows
-// per segment along eta.  The bottom wall row is produced with row 1 (its
+// and population), so no operand is selected after the read.  With FP32
+// arithmetic the LDS row holds backward differences of the values, each
+// lane's taken across the wavefront from its left neighbour, and both
+// directions apply Eq. (2.5) to differences.  The stored f-hat that the
+// exact final update of FP32SRF adds at stage C comes from a lane-private
+// LDS ring (populations 0-3) and from a second read of the row copied into
+// LDS by the buffer unit (populations 4-8).  The rows of the march are
+// unrolled five times so that ring slots are renamed, not moved.  The halo
+// costs 8 of 64 lanes across xi and 8 + 4 recomputed rows per segment along
+// eta.  The bottom wall row is produced with row 1 (its
 // extrapolation source), the lid row of f-hat(t + dt) with row ny - 2, the
 // lid row of f(t + dt/2) from row ny - 2 kept for one row in the LDS ring.
 //
