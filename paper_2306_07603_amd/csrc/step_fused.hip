@@ -121,15 +121,13 @@ struct MixedWeights {
     {
     }
     __device__ __forceinline__ T apply(T a2, T a1, T c0, T f1) const { return ((wc * c0 + wa1 * a1) + wa2 * a2) + wf * f1; }
-    // The same from the differences d1 = c0 - a1, d2 = a1 - a2, df = f1 - a1:
-    // eps df + (1 - eps) (3 d1 - d2).  Neighbouring values agree to many
-    // digits, so in FP32 the weighted sum of the values above loses to
-    // cancellation what the differences keep (an error of order one ulp of f
-    // per step that does not average out over a steady run).
-    __device__ __forceinline__ T apply_diff(T df, T d1, T d2) const { return (wc * d1 - wa2 * d2) + wf * df; }
-    // The same from backward differences B(m) = x(m) - x(m - 1) along the
-    // upwind direction: with n = B at the point (d1), f = B one further
-    // upwind (d2) and o = B one downwind (df = n + o),
+    // The same on differences, which FP32 arithmetic needs: neighbouring
+    // values agree to many digits, so the weighted sum of the values above
+    // loses to cancellation what differences keep (an error of order one ulp
+    // of f per step that does not average out over a steady run).  With the
+    // backward differences B(m) = x(m) - x(m - 1) along the upwind direction,
+    // n = B at the point (c0 - a1), f = B one further upwind (a1 - a2) and
+    // o = B one downwind (f1 - a1 = n + o), it is
     // (eps + 3 (1 - eps)) n - (1 - eps) f + eps o.
     __device__ __forceinline__ T apply_back(T n, T f, T o) const { return ((wc + wf) * n - wa2 * f) + wf * o; }
     // r minus the same, as three multiply-adds into r
