@@ -622,7 +622,9 @@ struct March {
                     dd[k] = equilibrium_k(Pd, uxd, uyd, k) - gd[k];
                     d[k] = T(dd[k]);
                 }
-                l = relaxation_time_d<IMPL>(dd, lam_old, pl);
+                // the second moments of Step (2) from the FP32 values of e - g: their sums need FP32 accuracy
+                // only, as the power law and the relaxation coefficients are FP32 in this mode
+                l = relaxation_time_d<IMPL>(d, lam_old, pl);
             } else {
                 moments(g, P, ux, uy);
                 equilibrium(P, ux, uy, e);
