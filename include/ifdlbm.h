@@ -198,6 +198,15 @@ int ifdlbm_get_fields_device(ifdlbm_t* h, int32_t cav, void* u, void* v, void* p
    range.  Errors: EINVAL (n < 0, or a NULL array with n > 0), EDEVICE. */
 int ifdlbm_round_stochastic_device(const double* v, const uint32_t* r16, float* out, int64_t n, void* hip_stream);
 
+/* The power of Step (2) in FP64 (Eq. 1.4: mu = K max(gamma^2, gamma_min^2)^((n - 1) / 2)) on its own, for tests
+   of the power routine of the FP64 step: out[i] = x[i]^y as the FP64 storage modes compute it, exp(y ln x) within
+   about two ulp.  The domain is that of the step: x[i] > 0 and finite (the clamped gamma^2) and |y ln x[i]| below
+   700; a NaN x[i] gives NaN, other values outside the domain give unspecified results.  x and out are
+   caller-owned device arrays of n elements (no handle; they may be the same array); the call runs on hip_stream
+   (NULL: the null stream) and returns when out is written.  Errors: EINVAL (n < 0, a NULL array with n > 0, or
+   y not finite), EDEVICE. */
+int ifdlbm_power_law_device(const double* x, double y, double* out, int64_t n, void* hip_stream);
+
 /* Kinetic energy of Eq. (5.1) of cavity cav: 1/2 sum |u|^2 over the physical area, trapezoid weights in
    (xi, eta) times the Jacobian J = 1 + 2 eta cot(theta). */
 int ifdlbm_kinetic_energy(ifdlbm_t* h, int32_t cav, double* energy);

@@ -20,6 +20,8 @@ namespace ifd {
 
 // out[i] = round_stochastic(v[i], r16[i] & 0xFFFF) for i < n (device arrays; kernels_common.hip)
 hipError_t launch_round_stochastic(const double* v, const uint32_t* r16, float* out, int64_t n, hipStream_t s);
+// out[i] = x[i]^y by the FP64 power of Step (2), for i < n (device arrays; kernels_common.hip)
+hipError_t launch_power_law(const double* x, double y, double* out, int64_t n, hipStream_t s);
 
 thread_local std::string g_last_error;
 
@@ -1242,6 +1244,17 @@ static int ifdlbm_round_stochastic_device_impl(const double* v, const uint32_t* 
     return IFDLBM_OK;
 }
 
+static int ifdlbm_power_law_device_impl(const double* x, double y, double* out, int64_t n, void* hip_stream)
+{
+    if (n < 0) return fail(IFDLBM_EINVAL, "power_law_device: n < 0");
+    if (n > 0 && (!x || !out)) return fail(IFDLBM_EINVAL, "power_law_device: NULL array");
+    if (!std::isfinite(y)) return fail(IFDLBM_EINVAL, "power_law_device: exponent not finite");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    IFD_HIP(launch_power_law(x, y, out, n, s));
+    IFD_HIP(hipStreamSynchronize(s));
+    return IFDLBM_OK;
+}
+
 #ifndef IFD_SOURCE_DIGEST
 #error "IFD_SOURCE_DIGEST: build the library with paper_2306_07603_amd/_build.py"
 #endif
@@ -1287,6 +1300,11 @@ int ifdlbm_get_fields_device(ifdlbm_t* h, int32_t cav, void* u, void* v, void* p
 int ifdlbm_round_stochastic_device(const double* v, const uint32_t* r16, float* out, int64_t n, void* hip_stream)
 {
     IFD_GUARD(ifdlbm_round_stochastic_device_impl(v, r16, out, n, hip_stream));
+}
+
+int ifdlbm_power_law_device(const double* x, double y, double* out, int64_t n, void* hip_stream)
+{
+    IFD_GUARD(ifdlbm_power_law_device_impl(x, y, out, n, hip_stream));
 }
 
 int ifdlbm_get_fields(ifdlbm_t* h, int32_t cav, double* u, double* v, double* p)

@@ -356,6 +356,22 @@ hipError_t launch_round_stochastic(const double* v, const uint32_t* r16, float* 
     return hipGetLastError();
 }
 
+// The FP64 power of Step (2) (Eq. 1.4 on gamma^2) on given values: out[i] =
+// x[i]^y as the FP64 arithmetic of the step computes it.
+__global__ void k_power_law(const double* x, double y, double* out, int64_t n)
+{
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+        out[q] = pow_pos<double>(x[q], y);
+}
+
+hipError_t launch_power_law(const double* x, double y, double* out, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_power_law, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, s, x, y, out, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_energy(int prec, const void* f, const CavityDesc*, const double*, int, const CavityDesc& hd,
                          double* partial, hipStream_t s)
 {

@@ -107,6 +107,8 @@ def lib():
                                                ctypes.c_int32]
         L.ifdlbm_round_stochastic_device.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                                      ctypes.c_void_p]
+        L.ifdlbm_power_law_device.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_int64,
+                                              ctypes.c_void_p]
         L.ifdlbm_kinetic_energy.argtypes = [_H, ctypes.c_int32, _D]
         L.ifdlbm_get_state.argtypes = [_H, ctypes.c_int32, _D, _D]
         L.ifdlbm_set_state.argtypes = [_H, ctypes.c_int32, _D, _D]
@@ -285,6 +287,18 @@ def ifdlbm_round_stochastic_device(v, r16, out, stream=None) -> None:
     s = (stream or torch.cuda.current_stream()).cuda_stream
     _check(lib().ifdlbm_round_stochastic_device(ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(r16.data_ptr()),
                                                 ctypes.c_void_p(out.data_ptr()), v.numel(), ctypes.c_void_p(s)))
+
+
+def ifdlbm_power_law_device(x, y: float, out, stream=None) -> None:
+    """The FP64 step's power x^y of Step (2) on device tensors: x and out float64, contiguous, with the same
+    number of elements; runs on `stream` (a torch stream, default the current one) and returns when out is
+    written."""
+    import torch
+    assert x.dtype == torch.float64 and out.dtype == torch.float64
+    assert x.is_contiguous() and out.is_contiguous() and x.numel() == out.numel() and x.is_cuda and out.is_cuda
+    s = (stream or torch.cuda.current_stream()).cuda_stream
+    _check(lib().ifdlbm_power_law_device(ctypes.c_void_p(x.data_ptr()), float(y), ctypes.c_void_p(out.data_ptr()),
+                                         x.numel(), ctypes.c_void_p(s)))
 
 
 def ifdlbm_kinetic_energy(h: Handle, cav: int) -> float:
