@@ -22,8 +22,8 @@
 // lane's taken across the wavefront from its left neighbour, and both
 // directions apply Eq. (2.5) to differences.  The stored f-hat that the
 // exact final update of FP32SRF adds at stage C comes from a lane-private
-// LDS ring (populations 0-3) and from a second read of the row copied into
-// LDS by the buffer unit (populations 4-8).  The rows of the march are
+// LDS ring (populations 0-5) and from a second read of the row copied into
+// LDS by the buffer unit (populations 6-8).  The rows of the march are
 // unrolled five times so that ring slots are renamed, not moved.  The halo
 // costs 8 of 64 lanes across xi and 8 + 4 recomputed rows per segment along
 // eta.  The bottom wall row is produced with row 1 (its
@@ -44,9 +44,12 @@ constexpr int kRing = 5;                         // ring slots: rows t - 4 .. t
 // Exact final update: stage C needs the stored f-hat of its row again.  Stage A
 // keeps populations 0 .. kGxRing - 1 of it in a lane-private LDS ring; the
 // buffer unit copies the others back from memory (by then the row has left L2).
-// Four ring populations fill the LDS of two waves per SIMD (20 240 bytes per
-// wave, 8 waves in the 160 KiB of a CU).
-constexpr int kGxRing = 4;
+// Six ring populations fill the LDS of two waves per SIMD (20 384 bytes per
+// wave, 8 waves in the 160 KiB of a CU) once the xi exchange of FP32SRF passes
+// one population at a time through a single LDS row.
+constexpr int kGxRing = 6;
+// populations per pass of the xi exchange through LDS
+constexpr int xs_rows(bool exact_final) { return exact_final ? 1 : 8; }
 
 // Waves per SIMD the register allocation must allow: two with FP32 arithmetic (256 VGPRs each), one with
 // FP64 arithmetic (its rings and stage temporaries take about 430 registers).
@@ -225,7 +228,7 @@ __device__ __forceinline__ T lds_at(const T* row, uint32_t byte_offset)
 // (exact final update), else 0.
 template <typename T, int NG>
 struct WaveLds {
-    T xs[8][kRowLds];                 // one row of each moving population, for the xi stencils
+    T xs[xs_rows(NG != 0)][kRowLds];  // one row of each moving population of a pass, for the xi stencils
     T hp[kRing][9][kWaveLanes];       // f-hat+ of rows t-4 .. t (lane-private); the slot of row ny keeps
                                       // f-bar of row ny-2 for the lid row of the half step
     T wb[2][9];                       // f-bar of columns 1 and nx-2 at the current half-step row
@@ -485,19 +488,27 @@ struct March {
                                               const MixedWeights<T>& my, bool elo, bool ehi, T (&out)[9])
     {
         auto& xs = sh.xs;
-        if constexpr (kDiffForm<T>) {
-            // the backward difference of each lane's value, its left neighbour's taken across the wavefront
-#pragma unroll
-            for (int k = 1; k < 9; ++k) xs[k - 1][lane + kPad] = ring[S2][k] - lane_below(ring[S2][k]);
-        } else {
-#pragma unroll
-            for (int k = 1; k < 9; ++k) xs[k - 1][lane + kPad] = ring[S2][k];
-        }
-        wave_sync();
         out[0] = base[0];
+        // the eight moving populations in passes of kXsRows through the exchange rows
+        constexpr int kXsRows = xs_rows(S::kExactFinal);
+        static_assert(8 % kXsRows == 0, "whole passes");
 #pragma unroll
         for (int k = 1; k < 9; ++k) {
-            const T* row = xs[k - 1];
+            const int x = (k - 1) % kXsRows;
+            if (x == 0) {
+                if (k > 1) wave_sync();   // the previous pass has read the rows
+                if constexpr (kDiffForm<T>) {
+                    // the backward difference of each lane's value, its left neighbour's taken across the wavefront
+#pragma unroll
+                    for (int m = k; m < k + kXsRows; ++m)
+                        xs[m - k][lane + kPad] = ring[S2][m] - lane_below(ring[S2][m]);
+                } else {
+#pragma unroll
+                    for (int m = k; m < k + kXsRows; ++m) xs[m - k][lane + kPad] = ring[S2][m];
+                }
+                wave_sync();
+            }
+            const T* row = xs[x];
             const T c0 = ring[S2][k];
             constexpr uint32_t E = sizeof(T);
             if constexpr (kDiffForm<T>) {
