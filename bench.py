@@ -239,7 +239,7 @@ def main() -> int:
     ap.add_argument("--precision", default="fp32srf", choices=["fp32srf", "fp32sr", "fp32", "fp32x", "fp16dev", "fp64"])
     ap.add_argument("--residual-every", type=int, default=100)
     ap.add_argument("--graph-steps", type=int, default=100)
-    ap.add_argument("--autotune-steps", type=int, default=10,
+    ap.add_argument("--autotune-steps", type=int, default=40,
                     help="steps per trial of the segment-length autotuner before timing (0: automatic choice)")
     ap.add_argument("--segment-rows", type=int, default=0,
                     help="force the fused kernel's row-segment length (skips the autotuner; for profiling runs)")
