@@ -52,7 +52,8 @@ def log(msg: str) -> None:
 
 
 # Kernel sources whose content the measured traffic belongs to: the traffic
-# record in profiles/ is used only while these files are unchanged.
+# record in profiles/ is used only while these files and the compiler flags
+# of step_fused.hip are unchanged.
 KERNEL_SOURCES = ["paper_2306_07603_amd/csrc/step_fused.hip", "paper_2306_07603_amd/csrc/lbm_device.h",
                   "paper_2306_07603_amd/csrc/ifdlbm_internal.h"]
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_fused_traffic_batch256.txt")
@@ -60,7 +61,9 @@ TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "k_fused_traffic_batch256.txt")
 
 def kernel_source_digest() -> str:
     import hashlib
+    from paper_2306_07603_amd import _build
     h = hashlib.sha256()
+    h.update(repr(_build.FILE_FLAGS.get("step_fused.hip", [])).encode())
     for rel in KERNEL_SOURCES:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())

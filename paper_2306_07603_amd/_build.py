@@ -21,6 +21,10 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-parameter",
 ]
+# Flags of single sources.  The step kernels are scheduled for instruction-level parallelism (LLVM's max-ilp
+# strategy) instead of occupancy first: they keep their occupancy either way (two waves per SIMD with FP32
+# arithmetic, one with FP64), and that schedule measured 0.5-2.2 % faster in every storage mode.
+FILE_FLAGS = {"step_fused.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
 
 
 def source_files():
@@ -30,10 +34,11 @@ def source_files():
 
 
 def source_digest() -> str:
-    """SHA-256 of the library's sources (names and contents), compiled into the library as
+    """SHA-256 of the library's sources (names and contents) and of the per-source flags, compiled into the library as
     ifdlbm_build_digest() so that the binding can refuse a library built from other sources."""
     import hashlib
     h = hashlib.sha256()
+    h.update(repr(sorted(FILE_FLAGS.items())).encode() + b"\0")
     for path in source_files():
         with open(path, "rb") as f:
             data = f.read()
@@ -42,7 +47,7 @@ def source_digest() -> str:
 
 
 def _compile(src: str, obj: str, extra) -> None:
-    cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *FILE_FLAGS.get(src, []), *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(" ".join(cmd) + "\n" + r.stdout + r.stderr)
